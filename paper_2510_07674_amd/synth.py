@@ -1,0 +1,306 @@
+"""Seeded synthetic workloads: towers in clutter on a random 7-DOF serial chain.
+
+This module only draws random problem descriptions (robot model, collision
+spheres, box clutter, blocks, skeleton, solver parameters).  It contains none of
+the method's arithmetic: no kinematics, no distances, no costs, no sampling of
+particles.  Both the FP64 oracle and the HIP path consume what it returns.
+
+The paper's own scenes (Sec. IV-C, Fig. "tower stacking", Table III) are not
+available; these synthetic towers-in-clutter stand in for them:
+
+* chain: classic DH, a ~ U[0, 0.1] m, d ~ U[0, 0.35] m, joint limits +-2.8 rad, base
+  at the world origin with z up, tool offset 0.10 m along the last joint axis; twists
+  alpha ~ U{-pi/2, +pi/2} on joints 1-6 and U{-pi/2, 0, +pi/2} on joint 7 (a zero twist
+  makes two consecutive axes parallel, and such chains rarely hold a block upright on
+  the table);
+* robot spheres (the paper represents the robot as spheres, Sec. III): spread
+  evenly by arc length along each link's polyline, radius ~ U[0.03, 0.08] m;
+* cube blocks of edge 0.05 m resting at random table poses, top-down grasp;
+* a 1 x 1 m table centred on the robot base (table top z = 0); blocks, goals and
+  the tower live in a placement region in front of the robot, 0.2-0.55 m out;
+* axis-aligned box obstacles with sides ~ U[0.05, 0.3] m resting anywhere on the
+  table, kept out of a square around the base and small squares around the blocks'
+  initial poses and around a hidden tower site, so that a placement exists.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+N_JOINTS = 7
+TABLE = (-0.5, 0.5, -0.5, 0.5)           # clutter table x_lo, x_hi, y_lo, y_hi; top at z = 0
+REGION = (0.2, 0.55, -0.35, 0.35)        # placement region (the problem's bounding box)
+
+MODE_TOWER = 0                           # block b goes to tower slot b (heights (b+1/2) h)
+MODE_FIXED = 1                           # block b goes to a given fixed pose
+
+# weight order shared by every consumer of Params.weights()
+WEIGHT_NAMES = ("stable", "height", "coll", "start", "tie", "arm", "block", "lim", "smooth")
+
+
+@dataclasses.dataclass
+class Problem:
+    dh: np.ndarray            # (7, 3) float64: a, d, alpha per joint
+    lo: np.ndarray            # (7,) joint lower limits
+    hi: np.ndarray            # (7,) joint upper limits
+    tool_d: float             # tool offset along the last joint axis
+    q_home: np.ndarray        # (7,) start configuration (pinned)
+    sph_link: np.ndarray      # (S,) int32, link index 1..7, non-decreasing
+    sph_c: np.ndarray         # (S, 3) centre in the link frame
+    sph_r: np.ndarray         # (S,) radius
+    boxes: np.ndarray         # (O, 6) centre xyz, half extents xyz (axis aligned)
+    h: float                  # block edge
+    block_init: np.ndarray    # (B, 4) x, y, z, yaw of the initial block poses
+    mode: int                 # MODE_TOWER or MODE_FIXED
+    goal: np.ndarray          # (B, 4) fixed goal poses (MODE_FIXED); tower: slot poses, xy unused
+    grasp: np.ndarray         # (3, 4) rigid transform G, block frame -> end-effector frame
+    table: np.ndarray         # (4,) placement region x_lo, x_hi, y_lo, y_hi
+    block_margin: float = 1e-3  # block collision spheres have radius h/4 - block_margin
+
+    @property
+    def S(self) -> int:
+        return int(self.sph_r.shape[0])
+
+    @property
+    def O(self) -> int:
+        return int(self.boxes.shape[0])
+
+    @property
+    def B(self) -> int:
+        return int(self.block_init.shape[0])
+
+
+@dataclasses.dataclass
+class Params:
+    # cost weights (the paper only says "scalar weights"): constraint terms dominate the
+    # smoothness objective so that the solution is feasible
+    w_stable: float = 1.0
+    w_height: float = 1.0
+    w_coll: float = 1.0
+    w_start: float = 10.0
+    w_tie: float = 10.0
+    w_arm: float = 1.0
+    w_block: float = 1.0
+    w_lim: float = 1.0
+    w_smooth: float = 1e-3
+    # stage 1: plain gradient descent, linear phase with eta_k = eta1 (1 - k/k_lin1),
+    # then k_quad1 quadratic steps at alpha1
+    k_lin1: int = 25
+    k_quad1: int = 5
+    eta1: float = 0.01
+    alpha1: float = 0.5
+    # stage 2: Adam under the same schedule shape; k_lin2 = round(lin_frac2 * K)
+    lin_frac2: float = 5.0 / 6.0
+    eta2: float = 1e-2
+    alpha2: float = 2e-4
+    beta1: float = 0.9
+    beta2: float = 0.999
+    adam_eps: float = 1e-8
+    # lift / initialisation
+    ik_iters: int = 50
+    ik_lambda: float = 0.05
+    ik_noise: float = 0.5
+    mid_noise: float = 0.5
+    # success test and stage-1 retries
+    sat_eps: float = 1e-3
+    retries: int = 4
+
+    def weights(self) -> np.ndarray:
+        return np.array([getattr(self, "w_" + n) for n in WEIGHT_NAMES], dtype=np.float64)
+
+    def k_lin2(self, K: int) -> int:
+        return int(round(self.lin_frac2 * K))
+
+
+@dataclasses.dataclass
+class SolveConfig:
+    N1: int          # stage-1 samples (0: fixed goals, no stage 1)
+    M: int           # particles kept after stage 1 = stage-2 particles
+    W: int           # waypoints per motion segment
+    K: int           # stage-2 iterations
+    seed: int = 0
+
+
+def _chain(rng: np.random.Generator):
+    a = rng.uniform(0.0, 0.1, N_JOINTS)
+    d = rng.uniform(0.0, 0.35, N_JOINTS)
+    alpha = np.concatenate([rng.choice(np.array([-math.pi / 2, math.pi / 2]), N_JOINTS - 1),
+                            rng.choice(np.array([-math.pi / 2, 0.0, math.pi / 2]), 1)])
+    dh = np.stack([a, d, alpha], axis=1)
+    lo = np.full(N_JOINTS, -2.8)
+    hi = np.full(N_JOINTS, 2.8)
+    return dh, lo, hi
+
+
+def _spheres(rng: np.random.Generator, dh: np.ndarray, S: int):
+    """Spread S spheres over the 7 links (first links get the remainder), evenly by arc
+    length along each link's polyline in its own frame: the previous joint origin
+    (-a, -d sin(alpha), -d cos(alpha)), the foot of the common normal (-a, 0, 0), and
+    the link origin (0, 0, 0)."""
+    per = [S // N_JOINTS + (1 if k < S % N_JOINTS else 0) for k in range(N_JOINTS)]
+    links, cents = [], []
+    for k in range(N_JOINTS):
+        a, d, al = dh[k]
+        p0 = np.array([-a, -d * math.sin(al), -d * math.cos(al)])
+        p1 = np.array([-a, 0.0, 0.0])
+        p2 = np.zeros(3)
+        l0 = float(np.linalg.norm(p1 - p0))
+        l1 = float(np.linalg.norm(p2 - p1))
+        tot = l0 + l1
+        for m in range(per[k]):
+            s = (m + 0.5) / per[k] * tot
+            if tot <= 0.0:
+                c = p2.copy()
+            elif s <= l0:
+                c = p0 + (p1 - p0) * (s / l0)
+            else:
+                c = p1 + (p2 - p1) * ((s - l0) / l1)
+            links.append(k + 1)
+            cents.append(c)
+    r = rng.uniform(0.03, 0.08, S)
+    return np.array(links, dtype=np.int32), np.array(cents), r
+
+
+def _keep_out(cx, cy, hx, hy, pts, rad):
+    for (px, py) in pts:
+        if abs(cx - px) < hx + rad and abs(cy - py) < hy + rad:
+            return True
+    return False
+
+
+def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
+                 h: float = 0.05) -> Problem:
+    """Draw one seeded problem.  Deterministic in (seed, B, O, S, mode, h)."""
+    rng = np.random.default_rng([seed, B, O, S, mode, 0x5A5A])
+    dh, lo, hi = _chain(rng)
+    sph_link, sph_c, sph_r = _spheres(rng, dh, S)
+    xlo, xhi, ylo, yhi = REGION
+    edge = 0.03
+
+    # initial block poses: separated discs in the placement region
+    pts = []
+    for _ in range(100000):
+        if len(pts) == B:
+            break
+        p = (rng.uniform(xlo + edge, xhi - edge), rng.uniform(ylo + edge, yhi - edge))
+        if all((p[0] - q[0]) ** 2 + (p[1] - q[1]) ** 2 > 0.08 ** 2 for q in pts):
+            pts.append(p)
+    if len(pts) < B:
+        raise ValueError("cannot place %d blocks in the placement region" % B)
+    yaw = rng.uniform(-math.pi, math.pi, B)
+    block_init = np.array([[pts[i][0], pts[i][1], h / 2, yaw[i]] for i in range(B)])
+
+    keep = list(pts)
+    goal = np.zeros((B, 4))
+    if mode == MODE_FIXED:
+        for i in range(B):
+            for _ in range(100000):
+                g = (rng.uniform(xlo + edge, xhi - edge), rng.uniform(ylo + edge, yhi - edge))
+                if all((g[0] - q[0]) ** 2 + (g[1] - q[1]) ** 2 > 0.12 ** 2 for q in keep):
+                    break
+            keep.append(g)
+            goal[i] = [g[0], g[1], h / 2, rng.uniform(-math.pi, math.pi)]
+    else:
+        for _ in range(1000):  # hidden tower site, kept free of clutter
+            g = (rng.uniform(xlo + 0.05, xhi - 0.05), rng.uniform(ylo + 0.05, yhi - 0.05))
+            if all((g[0] - q[0]) ** 2 + (g[1] - q[1]) ** 2 > 0.08 ** 2 for q in keep):
+                break
+        keep.append(g)
+        for i in range(B):
+            goal[i] = [math.nan, math.nan, (i + 0.5) * h, math.nan]
+
+    boxes = []
+    tries = 0
+    while len(boxes) < O and tries < 100000:
+        tries += 1
+        half = rng.uniform(0.05, 0.3, 3) / 2
+        cx = rng.uniform(TABLE[0], TABLE[1])
+        cy = rng.uniform(TABLE[2], TABLE[3])
+        if _keep_out(cx, cy, half[0], half[1], [(0.0, 0.0)], 0.2):
+            continue
+        if _keep_out(cx, cy, half[0], half[1], keep, 0.08):
+            continue
+        boxes.append([cx, cy, half[2], half[0], half[1], half[2]])
+    boxes = np.array(boxes, dtype=np.float64).reshape(-1, 6)
+
+    # top-down grasp: end effector at the top-face centre, its z axis pointing down
+    grasp = np.array([[1.0, 0.0, 0.0, 0.0],
+                      [0.0, -1.0, 0.0, 0.0],
+                      [0.0, 0.0, -1.0, h / 2]])
+    return Problem(dh=dh, lo=lo, hi=hi, tool_d=0.10, q_home=np.zeros(N_JOINTS),
+                   sph_link=sph_link, sph_c=sph_c, sph_r=sph_r, boxes=boxes, h=h,
+                   block_init=block_init, mode=mode, goal=goal, grasp=grasp,
+                   table=np.array(REGION, dtype=np.float64))
+
+
+# The five workloads.  C1..C3 are solve configurations, C4 is the differentiable-cost
+# batch, C5 is the serving mix (sizes drawn per request).
+def config(name: str, seed: int = 0):
+    """Return (problem, params, solve_config) for a named workload."""
+    if name == "tiny":           # 1 block to a fixed target, 10 boxes, 2 x 16 waypoints
+        prob = make_problem(seed, B=1, O=10, S=42, mode=MODE_FIXED)
+        return prob, Params(), SolveConfig(N1=0, M=64, W=16, K=50, seed=seed)
+    if name == "tower4":         # 4-block tower, 40 boxes, 8 x 32 waypoints
+        prob = make_problem(seed, B=4, O=40, S=42)
+        return prob, Params(), SolveConfig(N1=4096, M=1024, W=32, K=200, seed=seed)
+    if name == "tower10":        # 10-block tower, 80 boxes, 20 x 32 waypoints, 48 spheres
+        prob = make_problem(seed, B=10, O=80, S=48)
+        return prob, Params(), SolveConfig(N1=16384, M=2048, W=32, K=300, seed=seed)
+    raise KeyError(name)
+
+
+def serving_request(rng: np.random.Generator, seed: int):
+    """One request of the serving mix: blocks U{1..10}, obstacles U{0..80},
+    waypoints {16, 32} per segment, particle counts scaled with the block count."""
+    B = int(rng.integers(1, 11))
+    O = int(rng.integers(0, 81))
+    W = int(rng.choice([16, 32]))
+    P2 = int(min(max(128 * B, 128), 2048))
+    prob = make_problem(seed, B=B, O=O, S=42)
+    return prob, Params(), SolveConfig(N1=8 * P2, M=P2, W=W, K=50 + 25 * B, seed=seed)
+
+
+def random_states(rng: np.random.Generator, prob: Problem, P: int, W: int):
+    """Random stage-2 states for cost/gradient parity: joint angles uniform within
+    the limits (slightly beyond, so the limit hinge is exercised), block poses uniform
+    over the table at the tower slot heights with small height noise."""
+    B = prob.B
+    span = prob.hi - prob.lo
+    q = rng.uniform(prob.lo - 0.05 * span, prob.hi + 0.05 * span, size=(P, 2 * B, W, N_JOINTS))
+    pose = np.empty((P, B, 4))
+    xlo, xhi, ylo, yhi = prob.table
+    pose[..., 0] = rng.uniform(xlo, xhi, size=(P, B))
+    pose[..., 1] = rng.uniform(ylo, yhi, size=(P, B))
+    if prob.mode == MODE_FIXED:
+        pose[..., 2] = prob.goal[None, :, 2]
+    else:
+        pose[..., 2] = (np.arange(B) + 0.5)[None, :] * prob.h + rng.normal(0, 0.01, size=(P, B))
+    pose[..., 3] = rng.uniform(-math.pi, math.pi, size=(P, B))
+    return q, pose
+
+
+def random_placements(rng: np.random.Generator, prob: Problem, N: int):
+    """Random stage-1 states (x, y, yaw per block) uniform over the table."""
+    B = prob.B
+    xlo, xhi, ylo, yhi = prob.table
+    x = np.empty((N, B, 3))
+    x[..., 0] = rng.uniform(xlo, xhi, size=(N, B))
+    x[..., 1] = rng.uniform(ylo, yhi, size=(N, B))
+    x[..., 2] = rng.uniform(-math.pi, math.pi, size=(N, B))
+    return x
+
+
+def clustered_placements(rng: np.random.Generator, prob: Problem, N: int, spread: float = 0.03):
+    """Stage-1 states with the blocks stacked near one random spot, so that the
+    stability and block-block terms are active."""
+    B = prob.B
+    xlo, xhi, ylo, yhi = prob.table
+    x = np.empty((N, B, 3))
+    cx = rng.uniform(xlo + 0.1, xhi - 0.1, size=(N, 1))
+    cy = rng.uniform(ylo + 0.1, yhi - 0.1, size=(N, 1))
+    x[..., 0] = cx + rng.normal(0, spread, size=(N, B))
+    x[..., 1] = cy + rng.normal(0, spread, size=(N, B))
+    x[..., 2] = rng.uniform(-math.pi, math.pi, size=(N, B))
+    return x
