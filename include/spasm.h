@@ -1,0 +1,218 @@
+/* spasm.h -- C ABI of the MI355X (gfx950) SPaSM particle engine.
+ *
+ * SPaSM (Chen, Iyer, Kingston, "Differentiable Particle Optimization for Fast
+ * Sequential Manipulation", arXiv 2510.07674) solves pick-and-place for a given action
+ * skeleton in two stages: stage 1 samples and optimises block placements (Alg. 1),
+ * stage 2 lifts the surviving placements to joint-space trajectories and descends the
+ * whole trajectory together with the placements (Sec. III-B, Appendix B).  This library
+ * runs both stages as HIP kernels on the device; the caller owns every device buffer.
+ *
+ * Conventions shared by every entry point:
+ *   - All d_* arguments are device pointers (hipMalloc'd or torch tensors'
+ *     data_ptr()), contiguous, row-major, float32 unless stated.  Host pointers are
+ *     never retained past the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Device
+ *     entry points only enqueue work on it and return; spasm_solve synchronises it.
+ *   - A problem may be used from one stream at a time.  Calls on different problems are
+ *     independent.
+ *   - Return value: SPASM_OK or a negative status; spasm_last_error() returns a
+ *     thread-local message describing the last failure.  Invalid sizes, NULL buffers,
+ *     non-finite descriptions and unsupported shapes are rejected before any launch.
+ *     An infeasible problem is not an error: spasm_solve reports success = 0.
+ *
+ * State layouts (per particle p):
+ *   stage-1 placement  x    [N][B][3]      block x, y, yaw (z fixed at its slot)
+ *   stage-2 trajectory q    [P][2B][W][7]  segment s = 2b: transit to block b;
+ *                                          s = 2b+1: transfer of block b; the last
+ *                                          waypoint of s and the first of s+1 are copies
+ *                                          of one configuration
+ *   stage-2 placement  pose [P][B][4]      block x, y, z, yaw
+ */
+#ifndef SPASM_H
+#define SPASM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPASM_OK 0
+#define SPASM_EINVAL (-1)      /* bad argument: size, NULL, non-finite value */
+#define SPASM_ENOMEM (-2)      /* device allocation failed (problem_create only) */
+#define SPASM_EHIP (-3)        /* a HIP runtime call failed */
+#define SPASM_EUNSUPPORTED (-4) /* shape outside what the kernels support */
+#define SPASM_EBUSY (-5)       /* serving: no free slot or HBM budget */
+
+#define SPASM_STAGE_PLACE 1
+#define SPASM_STAGE_TRAJ 2
+#define SPASM_PHASE_LIN 0      /* residuals as they are (Sec. III-A, linear cost) */
+#define SPASM_PHASE_QUAD 1     /* squared residuals (quadratic refinement) */
+#define SPASM_MODE_TOWER 0     /* block b goes to tower slot b, centre height (b + 1/2) h */
+#define SPASM_MODE_FIXED 1     /* block b goes to goal[b] */
+
+typedef struct spasm_problem_s *spasm_problem;
+
+/* Serial chain: 7 revolute joints, classic DH A_k = Rz(q_k) Tz(d_k) Tx(a_k) Rx(alpha_k),
+ * base frame = world (z up), end effector T_E = T_7 Tz(tool_d). */
+typedef struct {
+    double dh[7][3];     /* a, d, alpha */
+    double lo[7], hi[7]; /* joint limits */
+    double tool_d;
+    double q_home[7];    /* start of the first segment when seeding trajectories */
+} spasm_chain_desc;
+
+/* Blocks and action skeleton: block b is picked from block_init[b] and placed either on
+ * the tower (slot b) or at goal[b]; blocks are moved in index order. */
+typedef struct {
+    int32_t n_blocks;         /* B >= 1 */
+    int32_t mode;             /* SPASM_MODE_TOWER or SPASM_MODE_FIXED */
+    double block_edge;        /* h: cube edge */
+    double block_margin;      /* block collision spheres have radius h/4 - margin */
+    const double *block_init; /* host [B][4] x, y, z, yaw */
+    const double *goal;       /* host [B][4] (SPASM_MODE_FIXED), ignored for towers */
+    double grasp[3][4];       /* G: block frame -> end-effector frame, [R | t] */
+    double region[4];         /* placement bounding box x_lo, x_hi, y_lo, y_hi */
+} spasm_skeleton_desc;
+
+/* Weights and schedules.  Stage 1 (Alg. 1): k_lin1 linear steps with
+ * eta_k = eta1 (1 - k / k_lin1), then k_quad1 quadratic steps at alpha1.  Stage 2: Adam
+ * (beta1, beta2, adam_eps, bias-corrected) under the same schedule shape over K steps
+ * with k_lin2 = round(lin_frac2 K), eta2, alpha2. */
+typedef struct {
+    double w[9];   /* stable, height, coll, start, tie, arm, block, lim, smooth */
+    int32_t k_lin1, k_quad1;
+    double eta1, alpha1;
+    double lin_frac2, eta2, alpha2, beta1, beta2, adam_eps;
+    int32_t ik_iters;
+    double ik_lambda, ik_noise, mid_noise;
+    double sat_eps;   /* a particle satisfies the constraints when its violation < sat_eps */
+    int32_t retries;  /* stage-1 resampling rounds when nothing satisfies */
+} spasm_params;
+
+typedef struct {
+    int32_t N1;    /* stage-1 samples; 0 = fixed goals, no stage 1 */
+    int32_t M;     /* particles kept after stage 1 = stage-2 particles */
+    int32_t W;     /* waypoints per segment: 4, 8, 16, 32 or 64 */
+    int32_t K;     /* stage-2 iterations */
+    uint64_t seed;
+} spasm_solve_config;
+
+typedef struct {
+    int32_t success;     /* 1 if the best particle's violation < sat_eps */
+    int32_t n_sat;       /* satisfying stage-2 particles */
+    int32_t stage1_sat;  /* satisfying stage-1 particles in the committed round (-1: none run) */
+    int32_t rounds;      /* stage-1 rounds run */
+    int32_t best;        /* index of the returned particle */
+    float viol, cost;    /* of the returned particle (quadratic phase) */
+    float length;        /* configuration-space path length sum |q_{w+1} - q_w| (rad) */
+    float stage1_ms, stage2_ms, total_ms;  /* device time (HIP events) */
+    float opt_ms;        /* the fused stage-2 descent launch alone */
+} spasm_result;
+
+/* --- problem -------------------------------------------------------------------------
+ * Copies the description to the current device (about 1-4 KB).  Spheres: n_sph of them,
+ * sph_link[i] in 1..7 non-decreasing, sph_c [n_sph][3] centres in the link frame,
+ * sph_r [n_sph] radii.  Obstacles: n_obs axis-aligned boxes [n_obs][6] centre and half
+ * extents (Sec. III: robot and objects as spheres, penetration penalties).  The problem
+ * owns its device copy until spasm_problem_destroy. */
+int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph, const int32_t *sph_link,
+                         const double *sph_c, const double *sph_r, int32_t n_obs,
+                         const double *boxes, const spasm_skeleton_desc *skel,
+                         const spasm_params *prm, spasm_problem *out);
+void spasm_problem_destroy(spasm_problem prob);
+int spasm_problem_blocks(spasm_problem prob);
+
+/* --- stage 1 --------------------------------------------------------------------------
+ * Alg. 1 SampleUniform: N placements, x and y uniform over the region shrunk by h/2, yaw
+ * uniform in [-pi, pi).  Philox4x64-10 with key (seed, 0) and counter (particle, block,
+ * round, 1); uniforms are the top 24 bits.  d_x: [N][B][3]. */
+int spasm_sample(spasm_problem prob, int32_t N, uint64_t seed, int32_t round, float *d_x,
+                 void *stream);
+
+/* --- costs ----------------------------------------------------------------------------
+ * Cost, violation and gradient of a batch (Appendix B).
+ * stage SPASM_STAGE_PLACE: d_x [P][B][3] placements; C_placement with z at the slot
+ *   heights; d_gx [P][B][3]; W and d_pose unused.
+ * stage SPASM_STAGE_TRAJ: d_x = q [P][2B][W][7], d_pose [P][B][4];
+ *   C_trajopt = C_placement(pose) + w_start C_start + w_tie C_tie + w_arm (C_arm + arm vs
+ *   blocks) + w_block C_block + w_lim C_lim + w_smooth C_smooth.  d_gx [P][2B][W][7] is the
+ *   gradient of every waypoint copy separately; d_gpose [P][B][4].
+ * d_cost [P], d_viol [P] (largest unsquared, unweighted residual).  d_gx / d_gpose may be
+ * NULL to compute costs only. */
+int spasm_cost_grad(spasm_problem prob, int32_t stage, int32_t phase, int32_t P, int32_t W,
+                    const float *d_x, const float *d_pose, float *d_cost, float *d_viol,
+                    float *d_gx, float *d_gpose, void *stream);
+
+/* Adjoint of the stage-2 cost for reverse-mode differentiation: given d_gout [P]
+ * (dL/dcost per particle) writes d_gq = gout * dcost/dq [P][2B][W][7] and
+ * d_gpose = gout * dcost/dpose [P][B][4]. */
+int spasm_cost_adjoint(spasm_problem prob, int32_t phase, int32_t P, int32_t W, const float *d_q,
+                       const float *d_pose, const float *d_gout, float *d_gq, float *d_gpose,
+                       void *stream);
+
+/* --- updates --------------------------------------------------------------------------
+ * Runs global schedule steps k_begin .. k_end-1 (1-based) in ONE launch, each a fused
+ * cost + gradient + update per particle with the state held on chip.
+ * stage 1 (Alg. 1 lines 5-14): gradient descent on d_x [P][B][3], x and y clamped into
+ *   the region shrunk by h/2; steps 1..k_lin1 linear, then quadratic; d_pose, d_opt unused.
+ * stage 2 (Sec. III-B): Adam on d_x = q [P][2B][W][7] and, for towers, d_pose [P][B][4];
+ *   K_total sets k_lin2; boundary copies get the sum of their gradients;
+ *   d_opt holds the Adam moments [P][(2B*W*7 + 4B) * 2] floats (m then v per particle),
+ *   read at entry and written back at exit; zero it before step 1.
+ * d_cost / d_viol (nullable, [P]) receive the quadratic-phase cost and violation of the
+ * final state. */
+int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, float *d_x,
+                   float *d_pose, float *d_opt, int32_t k_begin, int32_t k_end, int32_t K_total,
+                   float *d_cost, float *d_viol, void *stream);
+
+/* --- selection ------------------------------------------------------------------------
+ * Alg. 1 ArgSort[:M]: indices of the M smallest keys, ascending, equal keys in index
+ * order.  1 <= M <= N <= 16384.  d_key [N], d_idx [M] int32. */
+int spasm_select_topm(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *stream);
+
+/* Alg. 1 GetSatisfyingParticles + re-evaluated ArgSort: order of all n particles with the
+ * satisfying ones (viol < eps) first, each group by cost then index; d_nsat [1] int32
+ * receives the number of satisfying particles.  n <= 16384. */
+int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, int32_t *d_order,
+                int32_t *d_nsat, void *stream);
+
+/* --- lift and seeding (Sec. III-B) -----------------------------------------------------
+ * Damped least squares IK on the block frame T_E G^-1 (the paper allows any parallel
+ * IK): dq = J^T (J J^T + lambda^2 I)^-1 e, clamped to the limits.
+ * spasm_ik_iterate: n independent solves, in place on d_q [n][7], kind 0 = grasp (block
+ *   origin to target xyz, block z axis up, yaw free), kind 1 = place (x, y, z, yaw);
+ *   d_target [n][4].
+ * spasm_ik_lift: per particle and block, start at q_home + ik_noise U[-1,1]^7 (counter
+ *   (particle, 2b + chunk, 0, 2)), grasp at block_init[b], then place at d_pose[p][b]
+ *   starting from the grasp solution.  d_qgrasp, d_qplace [P][B][7]. */
+int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d_target, float *d_q,
+                     int32_t iters, void *stream);
+int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose, uint64_t seed, int32_t iters,
+                  float *d_qgrasp, float *d_qplace, void *stream);
+
+/* Straight-line seeds through one intermediate waypoint per segment: the midpoint of the
+ * segment's ends plus mid_noise U[-1,1]^7 (counter (particle, 2s + chunk, 0, 3)), at
+ * index (W-1)/2; the first segment starts at q_home.  d_q [P][2B][W][7]. */
+int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgrasp,
+                    const float *d_qplace, uint64_t seed, float *d_q, void *stream);
+
+/* --- whole method ------------------------------------------------------------------------
+ * Stage 1 (cfg->N1 > 0): sample N1, score (linear phase), keep the best M, descend,
+ * order satisfying first; resample up to `retries` more rounds while none satisfies
+ * (decided on the device).  Fixed goals (N1 = 0): every particle starts at the goals.
+ * Then lift, seed, K Adam steps, final quadratic-phase evaluation and the best particle.
+ * d_work: device workspace of spasm_solve_workspace() bytes (256-byte aligned).
+ * d_best_q [2B][W][7] and d_best_pose [B][4] receive the returned particle; *out the
+ * summary.  Synchronises the stream once at the end. */
+size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg);
+int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
+                float *d_best_q, float *d_best_pose, spasm_result *out, void *stream);
+
+const char *spasm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -541,8 +541,9 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
     }
 
     for (int j = 0; j < NJ; ++j) {
+        /* not a kink for parity: with FP32-exact limits and inputs both precisions take
+         * the same hinge decision */
         double eh = q[j] - pb->hi[j], el = pb->lo[j] - q[j];
-        so->kink = dmin(so->kink, dmin(fabs(eh), fabs(el)));
         if (eh > 0.0) {
             so->cost += w_lim * phi(phase, eh);
             so->viol = dmax(so->viol, eh);

@@ -1,0 +1,624 @@
+// C-ABI host side of the SPaSM engine: argument validation, problem packing and
+// upload, launch of the device pipeline.  No entry point computes anything on the host.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spasm.h"
+#include "spasm_internal.h"
+
+using namespace spasm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define SPASM_HIP(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(SPASM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool valid_W(int W) { return W == 4 || W == 8 || W == 16 || W == 32 || W == 64; }
+
+std::mutex g_attr_mu;
+bool g_attr_done[64];
+
+int ensure_attrs()
+{
+    int dev = 0;
+    SPASM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (dev >= 0 && dev < 64 && !g_attr_done[dev]) {
+        SPASM_HIP(set_smem_limits(MAX_SORT * sizeof(unsigned long long), 2 * NJ * MAX_THREADS * sizeof(float)));
+        g_attr_done[dev] = true;
+    }
+    return SPASM_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct spasm_problem_s {
+    KProb kp;
+    void *dmem = nullptr;
+    int device = 0;
+    int k_total1 = 0;
+    int retries = 0;
+    double lin_frac2 = 0.0;
+    float sat_eps = 1e-3f;
+    int ik_iters = 0;
+};
+
+extern "C" const char *spasm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph, const int32_t *sph_link,
+                                    const double *sph_c, const double *sph_r, int32_t n_obs, const double *boxes,
+                                    const spasm_skeleton_desc *skel, const spasm_params *prm, spasm_problem *out)
+{
+    if (!out) return fail(SPASM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!chain || !skel || !prm) return fail(SPASM_EINVAL, "chain, skeleton and params are required");
+    if (n_sph < 0 || n_obs < 0) return fail(SPASM_EINVAL, "negative sphere or obstacle count");
+    if (n_sph > 0 && (!sph_link || !sph_c || !sph_r)) return fail(SPASM_EINVAL, "sphere arrays are NULL");
+    if (n_obs > 0 && !boxes) return fail(SPASM_EINVAL, "obstacle array is NULL");
+    const int B = skel->n_blocks;
+    if (B < 1 || B > MAX_B) return fail(SPASM_EUNSUPPORTED, "n_blocks=%d outside 1..%d", B, MAX_B);
+    if (skel->mode != SPASM_MODE_TOWER && skel->mode != SPASM_MODE_FIXED)
+        return fail(SPASM_EINVAL, "unknown skeleton mode %d", skel->mode);
+    if (!skel->block_init) return fail(SPASM_EINVAL, "block_init is NULL");
+    if (skel->mode == SPASM_MODE_FIXED && !skel->goal) return fail(SPASM_EINVAL, "fixed goals need goal poses");
+    if (!finite_all(&chain->dh[0][0], 21) || !finite_all(chain->lo, 7) || !finite_all(chain->hi, 7) ||
+        !finite_all(chain->q_home, 7) || !std::isfinite(chain->tool_d))
+        return fail(SPASM_EINVAL, "non-finite chain description");
+    for (int j = 0; j < NJ; ++j)
+        if (!(chain->lo[j] <= chain->hi[j])) return fail(SPASM_EINVAL, "joint %d: lo > hi", j);
+    if (n_sph > 0 && (!finite_all(sph_c, (size_t)n_sph * 3) || !finite_all(sph_r, n_sph)))
+        return fail(SPASM_EINVAL, "non-finite sphere description");
+    for (int i = 0; i < n_sph; ++i) {
+        if (sph_link[i] < 1 || sph_link[i] > NJ) return fail(SPASM_EINVAL, "sphere %d: link %d outside 1..7", i, sph_link[i]);
+        if (i > 0 && sph_link[i] < sph_link[i - 1]) return fail(SPASM_EINVAL, "sphere links must be non-decreasing");
+        if (!(sph_r[i] > 0.0)) return fail(SPASM_EINVAL, "sphere %d: radius must be > 0", i);
+    }
+    if (n_obs > 0 && !finite_all(boxes, (size_t)n_obs * 6)) return fail(SPASM_EINVAL, "non-finite obstacle");
+    for (int o = 0; o < n_obs; ++o)
+        for (int c = 3; c < 6; ++c)
+            if (boxes[6 * o + c] < 0.0) return fail(SPASM_EINVAL, "obstacle %d: negative half extent", o);
+    if (!finite_all(skel->block_init, (size_t)B * 4) ||
+        (skel->mode == SPASM_MODE_FIXED && !finite_all(skel->goal, (size_t)B * 4)) ||
+        !finite_all(&skel->grasp[0][0], 12) || !finite_all(skel->region, 4) || !std::isfinite(skel->block_edge) ||
+        !std::isfinite(skel->block_margin))
+        return fail(SPASM_EINVAL, "non-finite skeleton description");
+    const double h = skel->block_edge;
+    if (!(h > 0.0)) return fail(SPASM_EINVAL, "block_edge must be > 0");
+    if (!(skel->block_margin >= 0.0 && skel->block_margin < 0.25 * h)) return fail(SPASM_EINVAL, "block_margin outside [0, h/4)");
+    if (!(skel->region[1] - skel->region[0] >= h && skel->region[3] - skel->region[2] >= h))
+        return fail(SPASM_EINVAL, "placement region smaller than a block");
+    // grasp must be a rigid transform
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double d = 0.0;
+            for (int k = 0; k < 3; ++k) d += skel->grasp[k][a] * skel->grasp[k][b];
+            if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-6) return fail(SPASM_EINVAL, "grasp rotation is not orthonormal");
+        }
+    if (!finite_all(prm->w, 9)) return fail(SPASM_EINVAL, "non-finite weights");
+    for (int i = 0; i < 9; ++i)
+        if (prm->w[i] < 0.0) return fail(SPASM_EINVAL, "negative weight %d", i);
+    if (prm->k_lin1 < 0 || prm->k_quad1 < 0 || prm->ik_iters < 0 || prm->retries < 0)
+        return fail(SPASM_EINVAL, "negative iteration count");
+    const double pv[] = {prm->eta1, prm->alpha1, prm->lin_frac2, prm->eta2, prm->alpha2, prm->beta1, prm->beta2,
+                         prm->adam_eps, prm->ik_lambda, prm->ik_noise, prm->mid_noise, prm->sat_eps};
+    if (!finite_all(pv, sizeof(pv) / sizeof(pv[0]))) return fail(SPASM_EINVAL, "non-finite parameter");
+    if (!(prm->beta1 >= 0 && prm->beta1 < 1 && prm->beta2 >= 0 && prm->beta2 < 1 && prm->adam_eps > 0))
+        return fail(SPASM_EINVAL, "Adam parameters outside their ranges");
+    if (!(prm->lin_frac2 >= 0.0 && prm->lin_frac2 <= 1.0)) return fail(SPASM_EINVAL, "lin_frac2 outside [0, 1]");
+
+    // sphere table, links padded to a multiple of the chunk size
+    int count[NJ] = {0};
+    for (int i = 0; i < n_sph; ++i) count[sph_link[i] - 1]++;
+    int maxper = 0;
+    for (int k = 0; k < NJ; ++k) maxper = std::max(maxper, count[k]);
+    const int chunk = maxper <= 4 ? 4 : maxper <= 6 ? 6 : maxper == 7 ? 7 : 8;
+    std::vector<float> sph;
+    int link_start[8];
+    link_start[0] = 0;
+    {
+        int src = 0;
+        for (int k = 0; k < NJ; ++k) {
+            const int padded = (count[k] + chunk - 1) / chunk * chunk;
+            for (int m = 0; m < padded; ++m) {
+                if (m < count[k]) {
+                    sph.push_back((float)sph_c[3 * src]);
+                    sph.push_back((float)sph_c[3 * src + 1]);
+                    sph.push_back((float)sph_c[3 * src + 2]);
+                    sph.push_back((float)sph_r[src]);
+                    ++src;
+                } else {  // never overlaps anything
+                    sph.push_back(0.f);
+                    sph.push_back(0.f);
+                    sph.push_back(0.f);
+                    sph.push_back(-1e30f);
+                }
+            }
+            link_start[k + 1] = (int)(sph.size() / 4);
+        }
+    }
+    std::vector<float> box((size_t)n_obs * 8);
+    for (int o = 0; o < n_obs; ++o) {
+        for (int c = 0; c < 3; ++c) {
+            box[8 * o + c] = (float)boxes[6 * o + c];
+            box[8 * o + 4 + c] = (float)boxes[6 * o + 3 + c];
+        }
+        box[8 * o + 3] = 0.f;
+        box[8 * o + 7] = 0.f;
+    }
+    auto pack_poses = [&](const double *src, std::vector<float> &dst) {
+        dst.assign((size_t)B * 8, 0.f);
+        for (int b = 0; b < B; ++b) {
+            for (int c = 0; c < 4; ++c) dst[8 * b + c] = (float)src[4 * b + c];
+            dst[8 * b + 4] = (float)std::cos(src[4 * b + 3]);
+            dst[8 * b + 5] = (float)std::sin(src[4 * b + 3]);
+        }
+    };
+    std::vector<float> init, goal;
+    pack_poses(skel->block_init, init);
+    if (skel->mode == SPASM_MODE_FIXED)
+        pack_poses(skel->goal, goal);
+    else
+        goal.assign((size_t)B * 8, 0.f);
+
+    const size_t off_sph = 0, n_sphf = sph.size();
+    const size_t off_box = align256((off_sph + n_sphf) * 4) / 4, n_boxf = box.size();
+    const size_t off_init = align256((off_box + n_boxf) * 4) / 4;
+    const size_t off_goal = align256((off_init + init.size()) * 4) / 4;
+    const size_t total = align256((off_goal + goal.size()) * 4);
+    std::vector<float> host(total / 4, 0.f);
+    std::copy(sph.begin(), sph.end(), host.begin() + off_sph);
+    std::copy(box.begin(), box.end(), host.begin() + off_box);
+    std::copy(init.begin(), init.end(), host.begin() + off_init);
+    std::copy(goal.begin(), goal.end(), host.begin() + off_goal);
+
+    auto *pb = new spasm_problem_s();
+    if (hipGetDevice(&pb->device) != hipSuccess) {
+        delete pb;
+        return fail(SPASM_EHIP, "hipGetDevice failed");
+    }
+    if (hipMalloc(&pb->dmem, total) != hipSuccess) {
+        delete pb;
+        return fail(SPASM_ENOMEM, "hipMalloc(%zu) failed", total);
+    }
+    if (hipMemcpy(pb->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(pb->dmem);
+        delete pb;
+        return fail(SPASM_EHIP, "problem upload failed");
+    }
+    float *base = (float *)pb->dmem;
+    KProb &K = pb->kp;
+    std::memset(&K, 0, sizeof(K));
+    K.sph = (const float4 *)(base + off_sph);
+    K.box = (const float4 *)(base + off_box);
+    K.blk_init = (const float4 *)(base + off_init);
+    K.goal = (const float4 *)(base + off_goal);
+    K.B = B;
+    K.S = link_start[7];
+    K.O = n_obs;
+    K.mode = skel->mode;
+    K.chunk = chunk;
+    for (int k = 0; k < 8; ++k) K.link_start[k] = link_start[k];
+    for (int j = 0; j < NJ; ++j) {
+        K.a[j] = (float)chain->dh[j][0];
+        K.d[j] = (float)chain->dh[j][1];
+        K.ca[j] = (float)std::cos(chain->dh[j][2]);
+        K.sa[j] = (float)std::sin(chain->dh[j][2]);
+        K.lo[j] = (float)chain->lo[j];
+        K.hi[j] = (float)chain->hi[j];
+        K.q_home[j] = (float)chain->q_home[j];
+    }
+    K.tool_d = (float)chain->tool_d;
+    K.h = (float)h;
+    K.half = (float)(0.5 * h);
+    K.r_blk = (float)(0.25 * h - skel->block_margin);
+    K.sph_off = (float)(0.25 * h);
+    {
+        const double xl = skel->region[0] + 0.5 * h, xh = skel->region[1] - 0.5 * h;
+        const double yl = skel->region[2] + 0.5 * h, yh = skel->region[3] - 0.5 * h;
+        K.samp_x0 = (float)xl;
+        K.samp_xs = (float)(xh - xl);
+        K.samp_y0 = (float)yl;
+        K.samp_ys = (float)(yh - yl);
+        K.clamp_xl = (float)xl;
+        K.clamp_xh = (float)xh;
+        K.clamp_yl = (float)yl;
+        K.clamp_yh = (float)yh;
+    }
+    for (int b = 0; b < B; ++b)
+        K.zstar[b] = (float)(skel->mode == SPASM_MODE_TOWER ? (b + 0.5) * h : skel->goal[4 * b + 2]);
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) K.Gi_R[3 * i + j] = (float)skel->grasp[j][i];
+        double t = 0.0;
+        for (int k = 0; k < 3; ++k) t -= skel->grasp[k][i] * skel->grasp[k][3];
+        K.Gi_t[i] = (float)t;
+    }
+    for (int i = 0; i < 9; ++i) K.w[i] = (float)prm->w[i];
+    K.k_lin1 = prm->k_lin1;
+    K.k_quad1 = prm->k_quad1;
+    K.eta1 = (float)prm->eta1;
+    K.alpha1 = (float)prm->alpha1;
+    K.eta2 = (float)prm->eta2;
+    K.alpha2 = (float)prm->alpha2;
+    K.beta1 = (float)prm->beta1;
+    K.beta2 = (float)prm->beta2;
+    K.adam_eps = (float)prm->adam_eps;
+    K.ik_iters = prm->ik_iters;
+    K.ik_lambda = (float)prm->ik_lambda;
+    K.ik_noise = (float)prm->ik_noise;
+    K.mid_noise = (float)prm->mid_noise;
+    K.sat_eps = (float)prm->sat_eps;
+    pb->k_total1 = prm->k_lin1 + prm->k_quad1;
+    pb->retries = prm->retries;
+    pb->lin_frac2 = prm->lin_frac2;
+    pb->sat_eps = (float)prm->sat_eps;
+    pb->ik_iters = prm->ik_iters;
+    *out = pb;
+    return SPASM_OK;
+}
+
+extern "C" void spasm_problem_destroy(spasm_problem prob)
+{
+    if (!prob) return;
+    if (prob->dmem) (void)hipFree(prob->dmem);
+    delete prob;
+}
+
+extern "C" int spasm_problem_blocks(spasm_problem prob) { return prob ? prob->kp.B : 0; }
+
+static int check_traj_shape(spasm_problem prob, int P, int W)
+{
+    if (P < 1) return fail(SPASM_EINVAL, "P=%d must be >= 1", P);
+    if (!valid_W(W)) return fail(SPASM_EUNSUPPORTED, "W=%d must be 4, 8, 16, 32 or 64", W);
+    if (2 * prob->kp.B * W > MAX_THREADS)
+        return fail(SPASM_EUNSUPPORTED, "2*B*W=%d exceeds %d waypoint slots per particle", 2 * prob->kp.B * W, MAX_THREADS);
+    return SPASM_OK;
+}
+
+extern "C" int spasm_sample(spasm_problem prob, int32_t N, uint64_t seed, int32_t round, float *d_x, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (N < 1 || !d_x) return fail(SPASM_EINVAL, "N must be >= 1 and d_x non-NULL");
+    SPASM_HIP(launch_sample(prob->kp, N, seed, round, d_x, nullptr, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_cost_grad(spasm_problem prob, int32_t stage, int32_t phase, int32_t P, int32_t W,
+                               const float *d_x, const float *d_pose, float *d_cost, float *d_viol, float *d_gx,
+                               float *d_gpose, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (phase != SPASM_PHASE_LIN && phase != SPASM_PHASE_QUAD) return fail(SPASM_EINVAL, "unknown phase %d", phase);
+    if (!d_x) return fail(SPASM_EINVAL, "d_x is NULL");
+    if (stage == SPASM_STAGE_PLACE) {
+        if (P < 1) return fail(SPASM_EINVAL, "P=%d must be >= 1", P);
+        SPASM_HIP(launch_place(prob->kp, P, d_x, nullptr, nullptr, 1, 1, phase, d_cost, d_viol, d_gx, nullptr,
+                               (hipStream_t)stream));
+        return SPASM_OK;
+    }
+    if (stage != SPASM_STAGE_TRAJ) return fail(SPASM_EINVAL, "unknown stage %d", stage);
+    int rc = check_traj_shape(prob, P, W);
+    if (rc) return rc;
+    if (!d_pose) return fail(SPASM_EINVAL, "d_pose is NULL");
+    TrajArgs a{};
+    a.P = P;
+    a.W = W;
+    a.phase = phase;
+    a.q_in = d_x;
+    a.pose_in = d_pose;
+    a.cost = d_cost;
+    a.viol = d_viol;
+    a.gq = d_gx;
+    a.gpose = d_gpose;
+    SPASM_HIP(launch_traj(prob->kp, (d_gx || d_gpose) ? 1 : 0, a, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_cost_adjoint(spasm_problem prob, int32_t phase, int32_t P, int32_t W, const float *d_q,
+                                  const float *d_pose, const float *d_gout, float *d_gq, float *d_gpose, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (phase != SPASM_PHASE_LIN && phase != SPASM_PHASE_QUAD) return fail(SPASM_EINVAL, "unknown phase %d", phase);
+    int rc = check_traj_shape(prob, P, W);
+    if (rc) return rc;
+    if (!d_q || !d_pose || !d_gout || !d_gq || !d_gpose) return fail(SPASM_EINVAL, "NULL buffer");
+    TrajArgs a{};
+    a.P = P;
+    a.W = W;
+    a.phase = phase;
+    a.q_in = d_q;
+    a.pose_in = d_pose;
+    a.gout = d_gout;
+    a.gq = d_gq;
+    a.gpose = d_gpose;
+    SPASM_HIP(launch_traj(prob->kp, 1, a, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, float *d_x, float *d_pose,
+                              float *d_opt, int32_t k_begin, int32_t k_end, int32_t K_total, float *d_cost,
+                              float *d_viol, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (!d_x) return fail(SPASM_EINVAL, "d_x is NULL");
+    if (k_begin < 1 || k_end < k_begin) return fail(SPASM_EINVAL, "step range [%d, %d) invalid", k_begin, k_end);
+    if (stage == SPASM_STAGE_PLACE) {
+        if (P < 1) return fail(SPASM_EINVAL, "P=%d must be >= 1", P);
+        if (k_end - 1 > prob->k_total1) return fail(SPASM_EINVAL, "stage-1 schedule has %d steps", prob->k_total1);
+        SPASM_HIP(launch_place(prob->kp, P, d_x, nullptr, d_x, k_begin, k_end, SPASM_PHASE_QUAD, d_cost, d_viol,
+                               nullptr, nullptr, (hipStream_t)stream));
+        return SPASM_OK;
+    }
+    if (stage != SPASM_STAGE_TRAJ) return fail(SPASM_EINVAL, "unknown stage %d", stage);
+    int rc = check_traj_shape(prob, P, W);
+    if (rc) return rc;
+    if (!d_pose) return fail(SPASM_EINVAL, "d_pose is NULL");
+    if (K_total < k_end - 1) return fail(SPASM_EINVAL, "K_total=%d shorter than the step range", K_total);
+    rc = ensure_attrs();
+    if (rc) return rc;
+    TrajArgs a{};
+    a.P = P;
+    a.W = W;
+    a.q_in = d_x;
+    a.pose_in = d_pose;
+    a.q_out = d_x;
+    a.pose_out = d_pose;
+    a.opt = d_opt;
+    a.k_begin = k_begin;
+    a.k_end = k_end;
+    a.k_lin2 = (int)std::lround(prob->lin_frac2 * K_total);
+    a.cost = d_cost;
+    a.viol = d_viol;
+    SPASM_HIP(launch_traj(prob->kp, 2, a, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_select_topm(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *stream)
+{
+    if (N < 1 || N > MAX_SORT) return fail(SPASM_EUNSUPPORTED, "N=%d outside 1..%d", N, MAX_SORT);
+    if (M < 1 || M > N) return fail(SPASM_EINVAL, "M=%d outside 1..N", M);
+    if (!d_key || !d_idx) return fail(SPASM_EINVAL, "NULL buffer");
+    int rc = ensure_attrs();
+    if (rc) return rc;
+    SPASM_HIP(launch_sort_keys(0, N, d_key, nullptr, 0.f, M, d_idx, nullptr, nullptr, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, int32_t *d_order,
+                           int32_t *d_nsat, void *stream)
+{
+    if (n < 1 || n > MAX_SORT) return fail(SPASM_EUNSUPPORTED, "n=%d outside 1..%d", n, MAX_SORT);
+    if (!d_cost || !d_viol || !d_order || !d_nsat) return fail(SPASM_EINVAL, "NULL buffer");
+    if (!std::isfinite(eps)) return fail(SPASM_EINVAL, "eps must be finite");
+    int rc = ensure_attrs();
+    if (rc) return rc;
+    SPASM_HIP(launch_sort_keys(1, n, d_cost, d_viol, eps, n, d_order, d_nsat, nullptr, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d_target, float *d_q,
+                                int32_t iters, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (kind != 0 && kind != 1) return fail(SPASM_EINVAL, "kind must be 0 (grasp) or 1 (place)");
+    if (n < 1 || iters < 0 || !d_target || !d_q) return fail(SPASM_EINVAL, "bad size or NULL buffer");
+    SPASM_HIP(launch_ik_iterate(prob->kp, kind, n, d_target, d_q, iters, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose, uint64_t seed, int32_t iters,
+                             float *d_qgrasp, float *d_qplace, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (P < 1 || iters < 0 || !d_pose || !d_qgrasp || !d_qplace) return fail(SPASM_EINVAL, "bad size or NULL buffer");
+    SPASM_HIP(launch_ik_lift(prob->kp, P, d_pose, seed, iters, d_qgrasp, d_qplace, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+extern "C" int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgrasp, const float *d_qplace,
+                               uint64_t seed, float *d_q, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    int rc = check_traj_shape(prob, P, W);
+    if (rc) return rc;
+    if (!d_qgrasp || !d_qplace || !d_q) return fail(SPASM_EINVAL, "NULL buffer");
+    SPASM_HIP(launch_traj_init(prob->kp, P, W, d_qgrasp, d_qplace, seed, d_q, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// whole method
+// ---------------------------------------------------------------------------------------
+namespace {
+struct SolveLayout {
+    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, pose, qg, qp, q, c2, v2, ord2, nsat2, info, finfo, total;
+};
+
+SolveLayout layout(const KProb &K, const spasm_solve_config &c)
+{
+    SolveLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t B = K.B, M = c.M, N1 = c.N1, W = c.W;
+    if (N1 > 0) {
+        L.x1 = take(N1 * B * 3 * 4);
+        L.c1 = take(N1 * 4);
+        L.v1 = take(N1 * 4);
+        L.idx = take(M * 4);
+        L.xs = take(M * B * 3 * 4);
+        L.cs = take(M * 4);
+        L.vs = take(M * 4);
+        L.ord1 = take(M * 4);
+        L.nsat1 = take(4);
+        L.done = take(4);
+    }
+    L.pose = take(M * B * 4 * 4);
+    L.qg = take(M * B * NJ * 4);
+    L.qp = take(M * B * NJ * 4);
+    L.q = take(M * 2 * B * W * NJ * 4);
+    L.c2 = take(M * 4);
+    L.v2 = take(M * 4);
+    L.ord2 = take(M * 4);
+    L.nsat2 = take(4);
+    L.info = take(8 * 4);
+    L.finfo = take(4 * 4);
+    L.total = off;
+    return L;
+}
+
+int check_cfg(spasm_problem prob, const spasm_solve_config *cfg)
+{
+    if (!prob || !cfg) return fail(SPASM_EINVAL, "problem and config are required");
+    if (cfg->M < 1 || cfg->M > MAX_SORT) return fail(SPASM_EUNSUPPORTED, "M=%d outside 1..%d", cfg->M, MAX_SORT);
+    if (prob->kp.mode == SPASM_MODE_TOWER) {
+        if (cfg->N1 < cfg->M || cfg->N1 > MAX_SORT)
+            return fail(SPASM_EUNSUPPORTED, "towers need M <= N1 <= %d (N1=%d)", MAX_SORT, cfg->N1);
+    } else if (cfg->N1 != 0) {
+        return fail(SPASM_EINVAL, "fixed-goal problems take N1 = 0");
+    }
+    if (cfg->K < 0) return fail(SPASM_EINVAL, "K must be >= 0");
+    return check_traj_shape(prob, cfg->M, cfg->W);
+}
+
+__global__ void k_zero_ints(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+extern "C" size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg)
+{
+    if (check_cfg(prob, cfg)) return 0;
+    return layout(prob->kp, *cfg).total;
+}
+
+extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
+                           float *d_best_q, float *d_best_pose, spasm_result *out, void *stream)
+{
+    int rc = check_cfg(prob, cfg);
+    if (rc) return rc;
+    if (!d_work || !d_best_q || !d_best_pose || !out) return fail(SPASM_EINVAL, "NULL buffer");
+    if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace must be 256-byte aligned");
+    const KProb &K = prob->kp;
+    const SolveLayout L = layout(K, *cfg);
+    if (work_bytes < L.total) return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, L.total);
+    rc = ensure_attrs();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)d_work;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    const int M = cfg->M, W = cfg->W;
+
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; ++i) SPASM_HIP(hipEventCreate(&ev[i]));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+
+    SPASM_HIP(hipEventRecord(ev[0], st));
+    if (cfg->N1 > 0) {
+        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, I(L.done), 1);
+        SPASM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, I(L.info), 8);
+        SPASM_HIP(hipGetLastError());
+        const int R = prob->retries;
+        for (int r = 0; r <= R; ++r) {
+            const int *skip = I(L.done);
+            SPASM_HIP(launch_sample(K, cfg->N1, cfg->seed, r, F(L.x1), skip, st));
+            SPASM_HIP(launch_place(K, cfg->N1, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1),
+                                   nullptr, skip, st));
+            SPASM_HIP(launch_sort_keys(0, cfg->N1, F(L.c1), nullptr, 0.f, M, I(L.idx), nullptr, skip, st));
+            SPASM_HIP(launch_place(K, M, F(L.x1), I(L.idx), F(L.xs), 1, prob->k_total1 + 1, SPASM_PHASE_QUAD,
+                                   F(L.cs), F(L.vs), nullptr, skip, st));
+            SPASM_HIP(launch_sort_keys(1, M, F(L.cs), F(L.vs), prob->sat_eps, M, I(L.ord1), I(L.nsat1), skip, st));
+            SPASM_HIP(launch_commit_stage1(K, M, r, r == R, F(L.xs), I(L.ord1), I(L.nsat1), F(L.pose), I(L.done),
+                                           I(L.info), st));
+        }
+    } else {
+        SPASM_HIP(launch_fixed_poses(K, M, F(L.pose), I(L.info), st));
+    }
+    SPASM_HIP(hipEventRecord(ev[1], st));
+    SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg->seed, prob->ik_iters, F(L.qg), F(L.qp), st));
+    SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), cfg->seed, F(L.q), st));
+    TrajArgs a{};
+    a.P = M;
+    a.W = W;
+    a.q_in = F(L.q);
+    a.pose_in = F(L.pose);
+    a.q_out = F(L.q);
+    a.pose_out = F(L.pose);
+    a.k_begin = 1;
+    a.k_end = cfg->K + 1;
+    a.k_lin2 = (int)std::lround(prob->lin_frac2 * cfg->K);
+    a.cost = F(L.c2);
+    a.viol = F(L.v2);
+    SPASM_HIP(hipEventRecord(ev[3], st));
+    SPASM_HIP(launch_traj(K, 2, a, st));
+    SPASM_HIP(hipEventRecord(ev[4], st));
+    SPASM_HIP(launch_sort_keys(1, M, F(L.c2), F(L.v2), prob->sat_eps, M, I(L.ord2), I(L.nsat2), nullptr, st));
+    SPASM_HIP(launch_finalize(K, M, W, F(L.q), F(L.pose), F(L.c2), F(L.v2), I(L.ord2), I(L.nsat2), d_best_q,
+                              d_best_pose, I(L.info), F(L.finfo), st));
+    SPASM_HIP(hipEventRecord(ev[2], st));
+    int32_t info[8];
+    float finfo[4];
+    SPASM_HIP(hipMemcpyAsync(info, I(L.info), sizeof(info), hipMemcpyDeviceToHost, st));
+    SPASM_HIP(hipMemcpyAsync(finfo, F(L.finfo), sizeof(finfo), hipMemcpyDeviceToHost, st));
+    SPASM_HIP(hipStreamSynchronize(st));
+    float t01 = 0.f, t12 = 0.f, t02 = 0.f, t34 = 0.f;
+    SPASM_HIP(hipEventElapsedTime(&t34, ev[3], ev[4]));
+    SPASM_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
+    SPASM_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
+    SPASM_HIP(hipEventElapsedTime(&t02, ev[0], ev[2]));
+    out->stage1_sat = info[0];
+    out->rounds = info[1];
+    out->n_sat = info[2];
+    out->best = info[3];
+    out->success = info[2] > 0;
+    out->viol = finfo[0];
+    out->cost = finfo[1];
+    out->length = finfo[2];
+    out->stage1_ms = t01;
+    out->stage2_ms = t12;
+    out->total_ms = t02;
+    out->opt_ms = t34;
+    return SPASM_OK;
+}

@@ -1,0 +1,1452 @@
+// gfx950 kernels of the SPaSM hot path (Chen, Iyer, Kingston, arXiv 2510.07674).
+//
+// Work mapping (wave64, no matrix cores: nothing here is a dense contraction):
+//   stage 1   one lane per (particle, block, block-sphere); 8 lanes per block reduce the
+//             block's pose gradient with lane shuffles, the particle's poses sit in LDS.
+//   stage 2   one workgroup per particle, one lane per waypoint slot (2B segments x W).
+//             Obstacle boxes and robot spheres are read with wave-uniform indices (scalar
+//             loads into SGPRs); block poses come from an LDS table.  The gradient is
+//             formed in reverse mode from per-link wrenches: a force f at point c on link
+//             l adds z_{j-1} . ((c - o_{j-1}) x f) to dC/dq_j for every j <= l.
+//   optimise  the whole schedule runs inside one launch with the state on chip
+//             (trajectory in VGPRs, Adam moments and poses in LDS).
+#include "spasm_internal.h"
+
+namespace spasm {
+
+// ------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float sgnf(float x) { return x >= 0.f ? 1.f : -1.f; }
+__device__ __forceinline__ float phi(int phase, float d) { return phase ? d * d : d; }
+__device__ __forceinline__ float dphi(int phase, float d) { return phase ? 2.f * d : 1.f; }
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Alg. 1 schedule: eta_k = eta (1 - k / k_lin) on the linear cost for k <= k_lin, then the
+// fixed rate alpha on the quadratic cost.
+__device__ __forceinline__ void schedule(int k, int k_lin, float eta, float alpha, int &phase, float &lr)
+{
+    if (k <= k_lin) {
+        phase = 0;
+        lr = eta * (1.f - (float)k / (float)k_lin);
+    } else {
+        phase = 1;
+        lr = alpha;
+    }
+}
+
+// Philox4x64-10 (Salmon et al., SC'11); 24-bit uniforms.
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+__device__ __forceinline__ void uniforms4(uint64_t seed, uint64_t a, uint64_t b, uint64_t c, uint64_t stream,
+                                          float u[4])
+{
+    uint64_t x[4] = {a, b, c, stream};
+    philox4x64(x, seed, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = (float)(x[i] >> 40) * (1.0f / 16777216.0f);
+}
+
+// Rigid frame: rotation columns x, y, z and origin p.
+struct Frame {
+    float x0, x1, x2, y0, y1, y2, z0, z1, z2, p0, p1, p2;
+};
+__device__ __forceinline__ void frame_identity(Frame &F)
+{
+    F.x0 = 1.f; F.x1 = 0.f; F.x2 = 0.f;
+    F.y0 = 0.f; F.y1 = 1.f; F.y2 = 0.f;
+    F.z0 = 0.f; F.z1 = 0.f; F.z2 = 1.f;
+    F.p0 = 0.f; F.p1 = 0.f; F.p2 = 0.f;
+}
+// T <- T Rz(q) Tz(d) Tx(a) Rx(alpha)  (classic DH)
+__device__ __forceinline__ void dh_step(Frame &F, float a, float d, float ca, float sa, float q)
+{
+    float s, c;
+    sincosf(q, &s, &c);
+    const float nx0 = c * F.x0 + s * F.y0, nx1 = c * F.x1 + s * F.y1, nx2 = c * F.x2 + s * F.y2;
+    const float u0 = c * F.y0 - s * F.x0, u1 = c * F.y1 - s * F.x1, u2 = c * F.y2 - s * F.x2;
+    const float ny0 = ca * u0 + sa * F.z0, ny1 = ca * u1 + sa * F.z1, ny2 = ca * u2 + sa * F.z2;
+    const float nz0 = ca * F.z0 - sa * u0, nz1 = ca * F.z1 - sa * u1, nz2 = ca * F.z2 - sa * u2;
+    F.p0 += a * nx0 + d * F.z0;
+    F.p1 += a * nx1 + d * F.z1;
+    F.p2 += a * nx2 + d * F.z2;
+    F.x0 = nx0; F.x1 = nx1; F.x2 = nx2;
+    F.y0 = ny0; F.y1 = ny1; F.y2 = ny2;
+    F.z0 = nz0; F.z1 = nz1; F.z2 = nz2;
+}
+
+// Box signed distance from the offsets d = p - centre and u = |d| - half extents:
+// outside |max(u,0)| with gradient sgn(d) max(u,0)/|max(u,0)|; inside the largest u with
+// the axis of the first largest component.
+__device__ __forceinline__ float box_sdf(float dx, float dy, float dz, float ux, float uy, float uz,
+                                         float &gx, float &gy, float &gz)
+{
+    const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
+    const float qq = qx * qx + qy * qy + qz * qz;
+    if (qq > 0.f) {
+        const float n = sqrtf(qq), inv = 1.f / n;
+        gx = sgnf(dx) * (qx * inv);
+        gy = sgnf(dy) * (qy * inv);
+        gz = sgnf(dz) * (qz * inv);
+        return n;
+    }
+    if (ux >= uy && ux >= uz) {
+        gx = sgnf(dx); gy = 0.f; gz = 0.f;
+        return ux;
+    }
+    if (uy >= uz) {
+        gx = 0.f; gy = sgnf(dy); gz = 0.f;
+        return uy;
+    }
+    gx = 0.f; gy = 0.f; gz = sgnf(dz);
+    return uz;
+}
+
+// ------------------------------------------------------------------------------------
+// Sphere sets against obstacles (axis-aligned boxes, scalar-loaded) and blocks (yawed
+// cubes from the LDS pose table).  CH spheres are tested per box so the box parameters
+// are fetched once per chunk; the exact distance and gradient run only in the (rare)
+// branch where some lane's sphere overlaps the box's slab test.
+// ------------------------------------------------------------------------------------
+template <bool GRAD, int CH>
+__device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
+                                              const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
+                                              bool act, float &cost, float &viol, float (&wf)[3], float (&wt)[3])
+{
+    for (int o = 0; o < P.O; ++o) {
+        const float4 bc = P.box[2 * o], be = P.box[2 * o + 1];
+        bool hit = false;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const float ux = fabsf(cx[i] - bc.x) - be.x;
+            const float uy = fabsf(cy[i] - bc.y) - be.y;
+            const float uz = fabsf(cz[i] - bc.z) - be.z;
+            hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
+        }
+        if (hit && act) {
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
+                const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
+                float gx, gy, gz;
+                const float sdf = box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
+                const float delta = r[i] - sdf;
+                if (delta > 0.f) {
+                    cost += wgt * phi(phase, delta);
+                    viol = fmaxf(viol, delta);
+                    if (GRAD) {
+                        const float sc = -wgt * dphi(phase, delta);
+                        const float fx = sc * gx, fy = sc * gy, fz = sc * gz;
+                        wf[0] += fx;
+                        wf[1] += fy;
+                        wf[2] += fz;
+                        wt[0] += cy[i] * fz - cz[i] * fy;
+                        wt[1] += cz[i] * fx - cx[i] * fz;
+                        wt[2] += cx[i] * fy - cy[i] * fx;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Blocks as they stand while the lane's segment runs: b' < b at the placement variable
+// (table 0, gradient flows to the pose), b' > b at the initial pose (table 1), block b
+// itself at its initial pose only for arm spheres during the transit before the grasp.
+template <bool GRAD, int CH>
+__device__ __forceinline__ void collide_blocks(const KProb &P, int phase, float wgt, const float (&cx)[CH],
+                                               const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
+                                               bool act, int b, bool own_visible, const float *s_pose,
+                                               float *s_pacc, float &cost, float &viol, float (&wf)[3],
+                                               float (&wt)[3])
+{
+    const int B = P.B;
+    const float half = P.half;
+    for (int bb = 0; bb < B; ++bb) {
+        const bool movable = bb < b;
+        const bool vis = act && (bb != b || own_visible);
+        const float *pp = s_pose + ((movable ? 0 : MAX_B) + bb) * 8;
+        const float tx = pp[0], ty = pp[1], tz = pp[2], cs = pp[4], sn = pp[5];
+        bool hit = false;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
+            const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
+            const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
+            hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
+        }
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+        if (hit && vis) {
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
+                const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
+                const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
+                float gx, gy, gz;
+                const float sdf = box_sdf(lx, ly, dz, ux, uy, uz, gx, gy, gz);
+                const float delta = r[i] - sdf;
+                if (delta > 0.f) {
+                    cost += wgt * phi(phase, delta);
+                    viol = fmaxf(viol, delta);
+                    if (GRAD) {
+                        const float sc = -wgt * dphi(phase, delta);
+                        const float wx = cs * gx - sn * gy, wy = sn * gx + cs * gy;  // world gradient
+                        const float fx = sc * wx, fy = sc * wy, fz = sc * gz;
+                        wf[0] += fx;
+                        wf[1] += fy;
+                        wf[2] += fz;
+                        wt[0] += cy[i] * fz - cz[i] * fy;
+                        wt[1] += cz[i] * fx - cx[i] * fz;
+                        wt[2] += cx[i] * fy - cy[i] * fx;
+                        if (movable) {
+                            g0 -= fx;
+                            g1 -= fy;
+                            g2 -= fz;
+                            g3 += sc * (gx * ly - gy * lx);
+                        }
+                    }
+                }
+            }
+        }
+        if (GRAD) {
+            if (__any(g0 != 0.f || g1 != 0.f || g2 != 0.f || g3 != 0.f)) {
+                g0 = wave_sum(g0);
+                g1 = wave_sum(g1);
+                g2 = wave_sum(g2);
+                g3 = wave_sum(g3);
+                if ((threadIdx.x & 63) == 0) {
+                    float *acc = s_pacc + bb * 4;
+                    acc[0] += g0;
+                    acc[1] += g1;
+                    acc[2] += g2;
+                    acc[3] += g3;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Placement cost lane (Appendix B, tower): sphere k of block i.  The lane owns the cost
+// of its sphere against obstacles, blocks placed above it (j > i, pose variables) and
+// blocks not moved yet (j > i, initial poses), and for k == 0 the height term and the
+// stability term of block i.  It returns the gradient with respect to block i's pose
+// (x, y, z, yaw) including the contributions of terms owned by other lanes (the pairs
+// (sphere of j < i, box i) and the stability terms of blocks below i), so that a sum
+// over the block's 8 lanes gives d cost / d pose_i without any scatter.
+// st: LDS pose table of the particle [B][8] = x, y, z, yaw, cos, sin.
+// ------------------------------------------------------------------------------------
+template <bool GRAD>
+__device__ void place_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost, float &viol,
+                           float (&g)[4])
+{
+    const int B = P.B;
+    const float w_coll = P.w[W_COLL], so = P.sph_off, rb = P.r_blk, half = P.half;
+    const float sbx = (k & 1) ? so : -so, sby = (k & 2) ? so : -so, sbz = (k & 4) ? so : -so;
+    const float xi = st[i * 8 + 0], yi = st[i * 8 + 1], zi = st[i * 8 + 2], ci = st[i * 8 + 4],
+                si = st[i * 8 + 5];
+    const float cx = xi + ci * sbx - si * sby, cy = yi + si * sbx + ci * sby, cz = zi + sbz;
+    const float dyx = -si * sbx - ci * sby, dyy = ci * sbx - si * sby;  // d c / d yaw
+
+    for (int o = 0; o < P.O; ++o) {
+        const float4 bc = P.box[2 * o], be = P.box[2 * o + 1];
+        const float dx = cx - bc.x, dy = cy - bc.y, dz = cz - bc.z;
+        const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
+        if (fmaxf(fmaxf(ux, uy), uz) < rb) {
+            float gx, gy, gz;
+            const float delta = rb - box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
+            if (delta > 0.f) {
+                cost += w_coll * phi(phase, delta);
+                viol = fmaxf(viol, delta);
+                if (GRAD) {
+                    const float sc = -w_coll * dphi(phase, delta);
+                    g[0] += sc * gx;
+                    g[1] += sc * gy;
+                    g[2] += sc * gz;
+                    g[3] += sc * (gx * dyx + gy * dyy);
+                }
+            }
+        }
+    }
+    for (int j = 0; j < B; ++j) {
+        // this sphere against block j > i, placed (table) and at its initial pose
+#pragma unroll
+        for (int tgt = 0; tgt < 2; ++tgt) {
+            float tx, ty, tz, cs, sn;
+            if (tgt == 0) {
+                tx = st[j * 8 + 0]; ty = st[j * 8 + 1]; tz = st[j * 8 + 2]; cs = st[j * 8 + 4]; sn = st[j * 8 + 5];
+            } else {
+                const float4 a0 = P.blk_init[2 * j], a1 = P.blk_init[2 * j + 1];
+                tx = a0.x; ty = a0.y; tz = a0.z; cs = a1.x; sn = a1.y;
+            }
+            const float dx = cx - tx, dy = cy - ty, dz = cz - tz;
+            const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
+            const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
+            if (j > i && fmaxf(fmaxf(ux, uy), uz) < rb) {
+                float gx, gy, gz;
+                const float delta = rb - box_sdf(lx, ly, dz, ux, uy, uz, gx, gy, gz);
+                if (delta > 0.f) {
+                    cost += w_coll * phi(phase, delta);
+                    viol = fmaxf(viol, delta);
+                    if (GRAD) {
+                        const float sc = -w_coll * dphi(phase, delta);
+                        const float wx = cs * gx - sn * gy, wy = sn * gx + cs * gy;
+                        g[0] += sc * wx;
+                        g[1] += sc * wy;
+                        g[2] += sc * gz;
+                        g[3] += sc * (wx * dyx + wy * dyy);
+                    }
+                }
+            }
+        }
+        // sphere k of block j < i against block i: gradient through block i's pose
+        if (GRAD && j < i) {
+            const float xj = st[j * 8 + 0], yj = st[j * 8 + 1], zj = st[j * 8 + 2], cj = st[j * 8 + 4],
+                        sj = st[j * 8 + 5];
+            const float px = xj + cj * sbx - sj * sby, py = yj + sj * sbx + cj * sby, pz = zj + sbz;
+            const float dx = px - xi, dy = py - yi, dz = pz - zi;
+            const float lx = ci * dx + si * dy, ly = ci * dy - si * dx;
+            const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
+            if (fmaxf(fmaxf(ux, uy), uz) < rb) {
+                float gx, gy, gz;
+                const float delta = rb - box_sdf(lx, ly, dz, ux, uy, uz, gx, gy, gz);
+                if (delta > 0.f) {
+                    const float sc = -w_coll * dphi(phase, delta);
+                    const float wx = ci * gx - si * gy, wy = si * gx + ci * gy;
+                    g[0] -= sc * wx;
+                    g[1] -= sc * wy;
+                    g[2] -= sc * gz;
+                    g[3] += sc * (gx * ly - gy * lx);
+                }
+            }
+        }
+    }
+    if (k == 0) {
+        const float w_h = P.w[W_HEIGHT], w_s = P.w[W_STABLE];
+        const float e = zi - P.zstar[i];
+        cost += w_h * e * e;
+        viol = fmaxf(viol, fabsf(e));
+        if (GRAD) g[2] += 2.f * w_h * e;
+        if (P.mode == 0) {
+            // C_stable terms m <= i: term m compares the mean xy of blocks above m with
+            // block m's h x h footprint
+            for (int m = 0; m + 1 < B; ++m) {
+                if (m > i) break;
+                float mx = 0.f, my = 0.f;
+                for (int j = m + 1; j < B; ++j) {
+                    mx += st[j * 8 + 0];
+                    my += st[j * 8 + 1];
+                }
+                const float n = (float)(B - 1 - m);
+                mx /= n;
+                my /= n;
+                const float cm = st[m * 8 + 4], sm = st[m * 8 + 5];
+                const float ex = mx - st[m * 8 + 0], ey = my - st[m * 8 + 1];
+                const float v0 = cm * ex + sm * ey, v1 = cm * ey - sm * ex;
+                const float a0 = fmaxf(fabsf(v0) - half, 0.f), a1 = fmaxf(fabsf(v1) - half, 0.f);
+                const float D = sqrtf(a0 * a0 + a1 * a1);
+                if (m == i) {
+                    cost += w_s * phi(phase, D);
+                    viol = fmaxf(viol, D);
+                }
+                if (GRAD && D > 0.f) {
+                    const float gw = w_s * dphi(phase, D);
+                    const float dv0 = sgnf(v0) * a0 / D, dv1 = sgnf(v1) * a1 / D;
+                    const float dm0 = cm * dv0 - sm * dv1, dm1 = sm * dv0 + cm * dv1;
+                    if (m == i) {
+                        g[0] -= gw * dm0;
+                        g[1] -= gw * dm1;
+                        g[3] += gw * (dv0 * v1 - dv1 * v0);
+                    } else {
+                        g[0] += gw * dm0 / n;
+                        g[1] += gw * dm1 / n;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 1: sampling, placement cost/gradient and the gradient-descent loop.
+// ------------------------------------------------------------------------------------
+__global__ void k_sample(KProb P, int N, uint64_t seed, int round, float *x, const int *skip)
+{
+    if (skip && *skip) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= N * P.B) return;
+    const int n = gid / P.B, i = gid % P.B;
+    float u[4];
+    uniforms4(seed, (uint64_t)n, (uint64_t)i, (uint64_t)round, 1u, u);
+    float *o = x + (size_t)gid * 3;
+    o[0] = P.samp_x0 + P.samp_xs * u[0];
+    o[1] = P.samp_y0 + P.samp_ys * u[1];
+    o[2] = -3.14159265358979f + 6.28318530717959f * u[2];
+}
+
+// One workgroup holds lcm(8B, 64) lanes = several particles; lane = (particle, block,
+// sphere).  Steps k_begin..k_end-1 of descent (clamped to the region), then one
+// evaluation at eval_phase.
+__global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_in, const int32_t *idx,
+                                                float *x_out, int k_begin, int k_end, int eval_phase,
+                                                float *cost_out, float *viol_out, float *gx_out, const int *skip)
+{
+    __shared__ float s_state[128 * 8];  // [particles per WG * B][8]
+    __shared__ float s_red[128][2];
+    if (skip && *skip) return;
+    const int B = P.B, per = 8 * B, ppw = blockDim.x / per;
+    const int tid = threadIdx.x, lp = tid / per, rem = tid % per, i = rem >> 3, k = rem & 7;
+    const int p = blockIdx.x * ppw + lp;
+    const bool valid = p < n;
+    float *st = s_state + lp * B * 8;
+    if (k == 0) {
+        float x = 0.f, y = 0.f, yaw = 0.f;
+        if (valid) {
+            const int src = idx ? idx[p] : p;
+            const float *xs = x_in + ((size_t)src * B + i) * 3;
+            x = xs[0];
+            y = xs[1];
+            yaw = xs[2];
+        }
+        float s, c;
+        sincosf(yaw, &s, &c);
+        st[i * 8 + 0] = x;
+        st[i * 8 + 1] = y;
+        st[i * 8 + 2] = P.zstar[i];
+        st[i * 8 + 3] = yaw;
+        st[i * 8 + 4] = c;
+        st[i * 8 + 5] = s;
+    }
+    __syncthreads();
+    for (int kk = k_begin; kk < k_end; ++kk) {
+        int phase;
+        float lr;
+        schedule(kk, P.k_lin1, P.eta1, P.alpha1, phase, lr);
+        float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
+        place_lane<true>(P, phase, i, k, st, c, v, g);
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+            g[0] += __shfl_xor(g[0], m, 64);
+            g[1] += __shfl_xor(g[1], m, 64);
+            g[3] += __shfl_xor(g[3], m, 64);
+        }
+        __syncthreads();
+        if (k == 0) {
+            const float x = fminf(fmaxf(st[i * 8 + 0] - lr * g[0], P.clamp_xl), P.clamp_xh);
+            const float y = fminf(fmaxf(st[i * 8 + 1] - lr * g[1], P.clamp_yl), P.clamp_yh);
+            const float yaw = st[i * 8 + 3] - lr * g[3];
+            float s, cc;
+            sincosf(yaw, &s, &cc);
+            st[i * 8 + 0] = x;
+            st[i * 8 + 1] = y;
+            st[i * 8 + 3] = yaw;
+            st[i * 8 + 4] = cc;
+            st[i * 8 + 5] = s;
+        }
+        __syncthreads();
+    }
+    float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
+    if (gx_out)
+        place_lane<true>(P, eval_phase, i, k, st, c, v, g);
+    else
+        place_lane<false>(P, eval_phase, i, k, st, c, v, g);
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        c += __shfl_xor(c, m, 64);
+        v = fmaxf(v, __shfl_xor(v, m, 64));
+        g[0] += __shfl_xor(g[0], m, 64);
+        g[1] += __shfl_xor(g[1], m, 64);
+        g[3] += __shfl_xor(g[3], m, 64);
+    }
+    if (k == 0) {
+        s_red[lp * B + i][0] = c;
+        s_red[lp * B + i][1] = v;
+    }
+    __syncthreads();
+    if (!valid) return;
+    if (k == 0) {
+        if (gx_out) {
+            float *o = gx_out + ((size_t)p * B + i) * 3;
+            o[0] = g[0];
+            o[1] = g[1];
+            o[2] = g[3];
+        }
+        if (x_out) {
+            float *o = x_out + ((size_t)p * B + i) * 3;
+            o[0] = st[i * 8 + 0];
+            o[1] = st[i * 8 + 1];
+            o[2] = st[i * 8 + 3];
+        }
+        if (i == 0) {
+            float cs = 0.f, vs = 0.f;
+            for (int j = 0; j < B; ++j) {
+                cs += s_red[lp * B + j][0];
+                vs = fmaxf(vs, s_red[lp * B + j][1]);
+            }
+            if (cost_out) cost_out[p] = cs;
+            if (viol_out) viol_out[p] = vs;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 2: one particle per workgroup, one waypoint slot per lane.
+// ------------------------------------------------------------------------------------
+struct Slot {
+    int s, w, b, tau;
+    bool active;
+};
+
+// Joint axis screw of joint j+1 from frame T_j: xi = (z_j, o_j x z_j).  For a wrench
+// (torque about the world origin t, force f) applied on links > j, <xi, (t, f)> is its
+// contribution to dC/dq_{j+1}.
+__device__ __forceinline__ float screw_dot(const Frame &F, const float (&wr)[6])
+{
+    const float m0 = F.p1 * F.z2 - F.p2 * F.z1, m1 = F.p2 * F.z0 - F.p0 * F.z2, m2 = F.p0 * F.z1 - F.p1 * F.z0;
+    return F.z0 * wr[0] + F.z1 * wr[1] + F.z2 * wr[2] + m0 * wr[3] + m1 * wr[4] + m2 * wr[5];
+}
+
+// Forward pass over the links, fully unrolled so that every per-joint value is a
+// register.  wr is the running wrench of all contacts on links < J+1 (torque about the
+// origin, force); before link J+1's contacts are added, <xi_{J+1}, wr> is subtracted
+// from g[J].  After the pass, g[j] + <xi_{j+1}, total wrench> is the reverse-mode
+// gradient sum over links >= j+1 (second pass in slot_eval).
+template <int J, bool GRAD, int CH>
+__device__ __forceinline__ void links_forward(const KProb &P, int phase, const Slot &sl, bool own_vis,
+                                              const float (&q)[NJ], const float *s_pose, float *s_pacc, Frame &F,
+                                              float &cost, float &viol, float (&g)[NJ], float (&wr)[6])
+{
+    if (GRAD) {
+        // evaluate here: sinking it would keep every joint's axis and wrench live
+        float t = screw_dot(F, wr);
+        asm volatile("" : "+v"(t));
+        g[J] -= t;
+    }
+    dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
+    float wt[3] = {wr[0], wr[1], wr[2]}, wf[3] = {wr[3], wr[4], wr[5]};
+    for (int s0 = P.link_start[J]; s0 < P.link_start[J + 1]; s0 += CH) {
+        float cx[CH], cy[CH], cz[CH], r[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const float4 sp = P.sph[s0 + i];
+            cx[i] = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
+            cy[i] = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
+            cz[i] = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
+            r[i] = sp.w;
+        }
+        collide_boxes<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, sl.active, cost, viol, wf, wt);
+        collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, sl.active, sl.b, own_vis, s_pose, s_pacc,
+                                 cost, viol, wf, wt);
+    }
+    wr[0] = wt[0]; wr[1] = wt[1]; wr[2] = wt[2];
+    wr[3] = wf[0]; wr[4] = wf[1]; wr[5] = wf[2];
+    if constexpr (J + 1 < NJ)
+        links_forward<J + 1, GRAD, CH>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
+}
+
+template <int J>
+__device__ __forceinline__ void links_reverse(const KProb &P, const float (&q)[NJ], Frame &F, float (&g)[NJ],
+                                              const float (&wr)[6])
+{
+    g[J] += screw_dot(F, wr);
+    if constexpr (J + 1 < NJ) {
+        dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
+        links_reverse<J + 1>(P, q, F, g, wr);
+    }
+}
+
+// Cost (and gradient) of one slot: arm spheres vs obstacles and blocks, held block,
+// grasp alignment, tie to the placement, joint limits.  Smoothness and the placement
+// cost are added by the caller.  GRAD: g[7] receives dC/dq of this slot, the pose
+// gradient goes to the wave's LDS accumulator (arm/held contacts with placed blocks)
+// and to s_tiepose (tie term).
+template <bool GRAD, int CH>
+__device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
+                                          const float *s_pose, float *s_pacc, float *s_tiepose, float &cost,
+                                          float &viol, float (&g)[NJ])
+{
+    const bool own_vis = sl.tau == 0 && sl.w < W - 1;
+    float wr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    Frame F;
+    frame_identity(F);
+    links_forward<0, GRAD, CH>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
+    float et[3] = {wr[0], wr[1], wr[2]}, ef[3] = {wr[3], wr[4], wr[5]};
+    // end effector and the block frame T_B = T_E G^-1
+    const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
+    const float *Gr = P.Gi_R;
+    // column c of R_B = R_E * (Gr[0][c], Gr[1][c], Gr[2][c])
+    float RB[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        RB[0][c] = Gr[c] * F.x0 + Gr[3 + c] * F.y0 + Gr[6 + c] * F.z0;
+        RB[1][c] = Gr[c] * F.x1 + Gr[3 + c] * F.y1 + Gr[6 + c] * F.z1;
+        RB[2][c] = Gr[c] * F.x2 + Gr[3 + c] * F.y2 + Gr[6 + c] * F.z2;
+    }
+    const float tb0 = pe0 + P.Gi_t[0] * F.x0 + P.Gi_t[1] * F.y0 + P.Gi_t[2] * F.z0;
+    const float tb1 = pe1 + P.Gi_t[0] * F.x1 + P.Gi_t[1] * F.y1 + P.Gi_t[2] * F.z1;
+    const float tb2 = pe2 + P.Gi_t[0] * F.x2 + P.Gi_t[1] * F.y2 + P.Gi_t[2] * F.z2;
+
+    // held block (Appendix B C_block, interior transfer waypoints)
+    const bool held = sl.active && sl.tau == 1 && sl.w >= 1 && sl.w <= W - 2;
+    if (__any(held)) {
+        const float so = P.sph_off, rb = P.r_blk;
+        float cx[8], cy[8], cz[8], r[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float s0 = (k & 1) ? so : -so, s1 = (k & 2) ? so : -so, s2 = (k & 4) ? so : -so;
+            cx[k] = tb0 + RB[0][0] * s0 + RB[0][1] * s1 + RB[0][2] * s2;
+            cy[k] = tb1 + RB[1][0] * s0 + RB[1][1] * s1 + RB[1][2] * s2;
+            cz[k] = tb2 + RB[2][0] * s0 + RB[2][1] * s1 + RB[2][2] * s2;
+            r[k] = rb;
+        }
+        const float w_block = P.w[W_BLOCK];
+        collide_boxes<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, held, cost, viol, ef, et);
+        collide_blocks<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, held, sl.b, false, s_pose, s_pacc, cost, viol,
+                                ef, et);
+    }
+    // grasp alignment at the first transfer waypoint (C_start: position, roll/pitch)
+    if (sl.active && sl.tau == 1 && sl.w == 0) {
+        const float w_st = P.w[W_START];
+        const float4 I = P.blk_init[2 * sl.b];
+        const float rp0 = tb0 - I.x, rp1 = tb1 - I.y, rp2 = tb2 - I.z;
+        const float u0 = RB[0][2], u1 = RB[1][2], u2 = RB[2][2];
+        const float rz0 = u0, rz1 = u1, rz2 = u2 - 1.f;
+        const float c2 = rp0 * rp0 + rp1 * rp1 + rp2 * rp2 + rz0 * rz0 + rz1 * rz1 + rz2 * rz2;
+        cost += w_st * c2;
+        viol = fmaxf(viol, sqrtf(c2));
+        if (GRAD) {
+            const float f0 = 2.f * w_st * rp0, f1 = 2.f * w_st * rp1, f2 = 2.f * w_st * rp2;
+            const float h0 = 2.f * w_st * rz0, h1 = 2.f * w_st * rz1, h2 = 2.f * w_st * rz2;
+            ef[0] += f0;
+            ef[1] += f1;
+            ef[2] += f2;
+            et[0] += tb1 * f2 - tb2 * f1 + u1 * h2 - u2 * h1;
+            et[1] += tb2 * f0 - tb0 * f2 + u2 * h0 - u0 * h2;
+            et[2] += tb0 * f1 - tb1 * f0 + u0 * h1 - u1 * h0;
+        }
+    }
+    // tie of the carried block to its placement variable at the last transfer waypoint
+    if (sl.active && sl.tau == 1 && sl.w == W - 1) {
+        const float w_t = P.w[W_TIE];
+        const float *pp = s_pose + sl.b * 8;
+        const float cps = pp[4], sps = pp[5];
+        const float rp0 = tb0 - pp[0], rp1 = tb1 - pp[1], rp2 = tb2 - pp[2];
+        const float ux0 = RB[0][0], ux1 = RB[1][0], ux2 = RB[2][0];
+        const float uz0 = RB[0][2], uz1 = RB[1][2], uz2 = RB[2][2];
+        const float rx0 = ux0 - cps, rx1 = ux1 - sps, rx2 = ux2;
+        const float rz0 = uz0, rz1 = uz1, rz2 = uz2 - 1.f;
+        const float c2 = rp0 * rp0 + rp1 * rp1 + rp2 * rp2 + rx0 * rx0 + rx1 * rx1 + rx2 * rx2 + rz0 * rz0 +
+                         rz1 * rz1 + rz2 * rz2;
+        cost += w_t * c2;
+        viol = fmaxf(viol, sqrtf(c2));
+        if (GRAD) {
+            const float f0 = 2.f * w_t * rp0, f1 = 2.f * w_t * rp1, f2 = 2.f * w_t * rp2;
+            const float hx0 = 2.f * w_t * rx0, hx1 = 2.f * w_t * rx1, hx2 = 2.f * w_t * rx2;
+            const float hz0 = 2.f * w_t * rz0, hz1 = 2.f * w_t * rz1, hz2 = 2.f * w_t * rz2;
+            ef[0] += f0;
+            ef[1] += f1;
+            ef[2] += f2;
+            et[0] += tb1 * f2 - tb2 * f1 + ux1 * hx2 - ux2 * hx1 + uz1 * hz2 - uz2 * hz1;
+            et[1] += tb2 * f0 - tb0 * f2 + ux2 * hx0 - ux0 * hx2 + uz2 * hz0 - uz0 * hz2;
+            et[2] += tb0 * f1 - tb1 * f0 + ux0 * hx1 - ux1 * hx0 + uz0 * hz1 - uz1 * hz0;
+            float *tp = s_tiepose + sl.b * 4;
+            tp[0] = -f0;
+            tp[1] = -f1;
+            tp[2] = -f2;
+            tp[3] = -(hx0 * -sps + hx1 * cps);
+        }
+    }
+    if (GRAD) {
+        const float wtot[6] = {et[0], et[1], et[2], ef[0], ef[1], ef[2]};
+        // Recompute the frames rather than keep all seven live across the contact loops;
+        // the opaque copy stops the compiler from merging the two passes.
+        float qr[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            qr[j] = q[j];
+            asm volatile("" : "+v"(qr[j]));
+        }
+        frame_identity(F);
+        links_reverse<0>(P, qr, F, g, wtot);
+    }
+    // joint-limit hinges
+    if (sl.active) {
+        const float w_l = P.w[W_LIM];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const float eh = q[j] - P.hi[j], el = P.lo[j] - q[j];
+            if (eh > 0.f) {
+                cost += w_l * phi(phase, eh);
+                viol = fmaxf(viol, eh);
+                if (GRAD) g[j] += w_l * dphi(phase, eh);
+            }
+            if (el > 0.f) {
+                cost += w_l * phi(phase, el);
+                viol = fmaxf(viol, el);
+                if (GRAD) g[j] -= w_l * dphi(phase, el);
+            }
+        }
+    }
+}
+
+// Whole-particle evaluation shared by every stage-2 mode: slot terms, smoothness (lane
+// shuffles: a segment is W consecutive lanes inside one wave) and the placement cost of
+// the pose variables (lanes tid < 8B, one block sphere each).
+template <bool GRAD, int CH>
+__device__ __forceinline__ void particle_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
+                                              const float *s_pose, float *s_pacc_wave, float *s_tiepose,
+                                              float *s_placeg, float &cost, float &viol, float (&g)[NJ])
+{
+    slot_eval<GRAD, CH>(P, phase, sl, W, q, s_pose, s_pacc_wave, s_tiepose, cost, viol, g);
+    const float w_s = P.w[W_SMOOTH];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const float qn = __shfl_down(q[j], 1, 64);
+        const float qp = __shfl_up(q[j], 1, 64);
+        if (sl.active && sl.w < W - 1) {
+            const float d = qn - q[j];
+            cost += w_s * d * d;
+            if (GRAD) g[j] -= 2.f * w_s * d;
+        }
+        if (GRAD && sl.active && sl.w > 0) g[j] += 2.f * w_s * (q[j] - qp);
+    }
+    const int tid = threadIdx.x;
+    if (tid < 8 * MAX_B) {
+        const int i = tid >> 3, k = tid & 7;
+        float gp[4] = {0.f, 0.f, 0.f, 0.f};
+        if (i < P.B) place_lane<GRAD>(P, phase, i, k, s_pose, cost, viol, gp);
+        if (GRAD) {
+#pragma unroll
+            for (int m = 1; m < 8; m <<= 1) {
+                gp[0] += __shfl_xor(gp[0], m, 64);
+                gp[1] += __shfl_xor(gp[1], m, 64);
+                gp[2] += __shfl_xor(gp[2], m, 64);
+                gp[3] += __shfl_xor(gp[3], m, 64);
+            }
+            if (k == 0 && i < P.B) {
+                s_placeg[i * 4 + 0] = gp[0];
+                s_placeg[i * 4 + 1] = gp[1];
+                s_placeg[i * 4 + 2] = gp[2];
+                s_placeg[i * 4 + 3] = gp[3];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void set_pose_entry(float *s_pose, int b, float x, float y, float z, float yaw)
+{
+    float s, c;
+    sincosf(yaw, &s, &c);
+    float *pp = s_pose + b * 8;
+    pp[0] = x;
+    pp[1] = y;
+    pp[2] = z;
+    pp[3] = yaw;
+    pp[4] = c;
+    pp[5] = s;
+}
+
+__device__ __forceinline__ float adam_update(float x, float &m, float &v, float g, float lr, float b1, float b2,
+                                             float eps, float bc1, float bc2s)
+{
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    return x - (lr / bc1) * m / (sqrtf(v) / bc2s + eps);
+}
+
+// MODE 0: cost, 1: cost + gradient (optionally scaled per particle), 2: optimise.
+template <int MODE, int CH>
+__global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
+{
+    __shared__ float s_pose[2 * MAX_B * 8];
+    __shared__ float s_pacc[16 * MAX_B * 4];
+    __shared__ float s_tiepose[MAX_B * 4];
+    __shared__ float s_placeg[MAX_B * 4];
+    __shared__ float s_tie[2][2 * MAX_B][8];
+    __shared__ float s_red[16][2];
+    __shared__ float s_popt[2][MAX_B * 4];
+    extern __shared__ float s_mv[];  // MODE 2: [2][NJ][blockDim.x] Adam moments
+
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int B = P.B, W = a.W, NS = 2 * B, BW = B * W;
+    Slot sl;
+    sl.active = tid < 2 * BW;
+    if (tid < BW) {
+        sl.s = 2 * (tid / W);
+        sl.w = tid % W;
+    } else if (sl.active) {
+        const int t2 = tid - BW;
+        sl.s = 2 * (t2 / W) + 1;
+        sl.w = t2 % W;
+    } else {
+        sl.s = 0;
+        sl.w = 0;
+    }
+    sl.b = sl.s >> 1;
+    sl.tau = sl.s & 1;
+    const size_t qoff = (((size_t)p * NS + sl.s) * W + sl.w) * NJ;
+    float q[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) q[j] = sl.active ? a.q_in[qoff + j] : 0.f;
+    if (tid < B) {
+        const float *pi = a.pose_in + ((size_t)p * B + tid) * 4;
+        set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3]);
+    } else if (tid < 2 * B) {  // blockDim >= 64 >= 2 * MAX_B
+        const int b = tid - B;
+        const float4 a0 = P.blk_init[2 * b], a1 = P.blk_init[2 * b + 1];
+        float *pp = s_pose + (MAX_B + b) * 8;
+        pp[0] = a0.x;
+        pp[1] = a0.y;
+        pp[2] = a0.z;
+        pp[3] = a0.w;
+        pp[4] = a1.x;
+        pp[5] = a1.y;
+    }
+    float *s_pacc_w = s_pacc + wave * MAX_B * 4;
+    if (lane < 4 * B) s_pacc_w[lane] = 0.f;
+    const size_t per_opt = (size_t)2 * BW * NJ + 4 * B;
+    if (MODE == 2) {
+        const float *om = a.opt ? a.opt + (size_t)p * 2 * per_opt : nullptr;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            s_mv[(0 * NJ + j) * blockDim.x + tid] = (om && sl.active) ? om[(sl.s * W + sl.w) * NJ + j] : 0.f;
+            s_mv[(1 * NJ + j) * blockDim.x + tid] =
+                (om && sl.active) ? om[per_opt + (sl.s * W + sl.w) * NJ + j] : 0.f;
+        }
+        if (tid < 4 * B) {
+            s_popt[0][tid] = om ? om[2 * BW * NJ + tid] : 0.f;
+            s_popt[1][tid] = om ? om[per_opt + 2 * BW * NJ + tid] : 0.f;
+        }
+    }
+    __syncthreads();
+
+    if (MODE == 2) {
+        const float b1 = P.beta1, b2 = P.beta2, eps = P.adam_eps;
+        for (int k = a.k_begin; k < a.k_end; ++k) {
+            int phase;
+            float lr;
+            schedule(k, a.k_lin2, P.eta2, P.alpha2, phase, lr);
+            float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            particle_eval<true, CH>(P, phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+            if (sl.active && sl.w == W - 1)
+                for (int j = 0; j < NJ; ++j) s_tie[0][sl.s][j] = g[j];
+            if (sl.active && sl.w == 0)
+                for (int j = 0; j < NJ; ++j) s_tie[1][sl.s][j] = g[j];
+            __syncthreads();
+            const float bc1 = 1.f - powf(b1, (float)k), bc2s = sqrtf(1.f - powf(b2, (float)k));
+            if (sl.active) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    float gj = g[j];
+                    if (sl.w == W - 1 && sl.s + 1 < NS) gj = g[j] + s_tie[1][sl.s + 1][j];
+                    if (sl.w == 0 && sl.s > 0) gj = s_tie[0][sl.s - 1][j] + g[j];
+                    float &m = s_mv[(0 * NJ + j) * blockDim.x + tid];
+                    float &v = s_mv[(1 * NJ + j) * blockDim.x + tid];
+                    float mm = m, vv = v;
+                    q[j] = adam_update(q[j], mm, vv, gj, lr, b1, b2, eps, bc1, bc2s);
+                    m = mm;
+                    v = vv;
+                }
+            }
+            if (P.mode == 0 && tid < 4 * B) {
+                const int bb = tid >> 2, c = tid & 3;
+                float gsum = 0.f;
+                for (int wv = 0; wv < nwave; ++wv) gsum += s_pacc[(wv * MAX_B + bb) * 4 + c];
+                gsum += s_placeg[bb * 4 + c];
+                gsum += s_tiepose[bb * 4 + c];
+                float mm = s_popt[0][tid], vv = s_popt[1][tid];
+                const float x = adam_update(s_pose[bb * 8 + c], mm, vv, gsum, lr, b1, b2, eps, bc1, bc2s);
+                s_popt[0][tid] = mm;
+                s_popt[1][tid] = vv;
+                s_pose[bb * 8 + c] = x;
+                if (c == 3) {
+                    float s, cc;
+                    sincosf(x, &s, &cc);
+                    s_pose[bb * 8 + 4] = cc;
+                    s_pose[bb * 8 + 5] = s;
+                }
+            }
+            __syncthreads();
+            if (lane < 4 * B) s_pacc_w[lane] = 0.f;
+        }
+        // write the state back, then evaluate the final state (quadratic phase)
+        if (sl.active) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) a.q_out[qoff + j] = q[j];
+        }
+        if (tid < 4 * B) {
+            const int bb = tid >> 2, c = tid & 3;
+            a.pose_out[((size_t)p * B + bb) * 4 + c] = s_pose[bb * 8 + c];
+        }
+        if (a.opt) {
+            float *om = a.opt + (size_t)p * 2 * per_opt;
+            if (sl.active)
+                for (int j = 0; j < NJ; ++j) {
+                    om[(sl.s * W + sl.w) * NJ + j] = s_mv[(0 * NJ + j) * blockDim.x + tid];
+                    om[per_opt + (sl.s * W + sl.w) * NJ + j] = s_mv[(1 * NJ + j) * blockDim.x + tid];
+                }
+            if (tid < 4 * B) {
+                om[2 * BW * NJ + tid] = s_popt[0][tid];
+                om[per_opt + 2 * BW * NJ + tid] = s_popt[1][tid];
+            }
+        }
+        if (!a.cost && !a.viol) return;
+        float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        particle_eval<false, CH>(P, 1, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+        cost = wave_sum(cost);
+        viol = wave_max(viol);
+        if (lane == 0) {
+            s_red[wave][0] = cost;
+            s_red[wave][1] = viol;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float c = 0.f, v = 0.f;
+            for (int wv = 0; wv < nwave; ++wv) {
+                c += s_red[wv][0];
+                v = fmaxf(v, s_red[wv][1]);
+            }
+            if (a.cost) a.cost[p] = c;
+            if (a.viol) a.viol[p] = v;
+        }
+        return;
+    }
+
+    // MODE 0 / 1: one evaluation
+    float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    particle_eval<MODE == 1, CH>(P, a.phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+    cost = wave_sum(cost);
+    viol = wave_max(viol);
+    if (lane == 0) {
+        s_red[wave][0] = cost;
+        s_red[wave][1] = viol;
+    }
+    __syncthreads();
+    const float scale = a.gout ? a.gout[p] : 1.f;
+    if (tid == 0) {
+        float c = 0.f, v = 0.f;
+        for (int wv = 0; wv < nwave; ++wv) {
+            c += s_red[wv][0];
+            v = fmaxf(v, s_red[wv][1]);
+        }
+        if (a.cost) a.cost[p] = c;
+        if (a.viol) a.viol[p] = v;
+    }
+    if (MODE == 1) {
+        if (sl.active && a.gq) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) a.gq[qoff + j] = g[j] * scale;
+        }
+        if (a.gpose && tid < 4 * B) {
+            const int bb = tid >> 2, c = tid & 3;
+            float gsum = 0.f;
+            for (int wv = 0; wv < nwave; ++wv) gsum += s_pacc[(wv * MAX_B + bb) * 4 + c];
+            gsum += s_placeg[bb * 4 + c];
+            gsum += s_tiepose[bb * 4 + c];
+            a.gpose[((size_t)p * B + bb) * 4 + c] = gsum * scale;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Selection: one workgroup sorts up to 16384 64-bit keys in LDS (bitonic).
+// kind 0 (top-M):  key = ordered(cost) << 32 | index
+// kind 1 (order):  key = unsatisfied << 63 | cost bits << 32 | index   (cost >= 0)
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    if (f != f) f = __int_as_float(0x7f800000);
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(1024) void k_sort(int kind, int n, const float *cost, const float *viol, float eps,
+                                               int M, int32_t *out_idx, int32_t *out_count, const int *skip)
+{
+    extern __shared__ unsigned long long s_keys[];
+    __shared__ int s_cnt;
+    if (skip && *skip) return;
+    const int tid = threadIdx.x;
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    if (tid == 0) s_cnt = 0;
+    int cnt = 0;
+    for (int i = tid; i < npow; i += blockDim.x) {
+        unsigned long long key = ~0ull;
+        if (i < n) {
+            if (kind == 0) {
+                key = ((unsigned long long)ordered_bits(cost[i]) << 32) | (unsigned)i;
+            } else {
+                float c = cost[i];
+                if (c != c) c = __int_as_float(0x7f800000);
+                c = fmaxf(c, 0.f);
+                const bool unsat = !(viol[i] < eps);
+                cnt += !unsat;
+                key = ((unsigned long long)unsat << 63) | ((unsigned long long)(__float_as_uint(c) & 0x7fffffffu) << 32) |
+                      (unsigned)i;
+            }
+        }
+        s_keys[i] = key;
+    }
+    __syncthreads();
+    if (cnt) atomicAdd(&s_cnt, cnt);
+    for (int k = 2; k <= npow; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < npow; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long x = s_keys[i], y = s_keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s_keys[i] = y;
+                        s_keys[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int nout = kind == 0 ? M : n;
+    for (int i = tid; i < nout; i += blockDim.x) out_idx[i] = (int32_t)(s_keys[i] & 0xffffffffu);
+    if (tid == 0 && out_count) *out_count = kind == 0 ? M : s_cnt;
+}
+
+// ------------------------------------------------------------------------------------
+// Lift (damped least squares on the block frame) and trajectory seeding.
+// ------------------------------------------------------------------------------------
+__device__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ], int iters)
+{
+    float sy, cy;
+    sincosf(tyaw, &sy, &cy);
+    const float lam2 = P.ik_lambda * P.ik_lambda;
+    for (int it = 0; it < iters; ++it) {
+        float ax[NJ][6];  // o_{j-1}, z_{j-1}
+        Frame F;
+        frame_identity(F);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            ax[j][0] = F.p0; ax[j][1] = F.p1; ax[j][2] = F.p2;
+            ax[j][3] = F.z0; ax[j][4] = F.z1; ax[j][5] = F.z2;
+            dh_step(F, P.a[j], P.d[j], P.ca[j], P.sa[j], q[j]);
+        }
+        const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
+        const float *Gr = P.Gi_R;
+        float RB[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            RB[0][c] = Gr[c] * F.x0 + Gr[3 + c] * F.y0 + Gr[6 + c] * F.z0;
+            RB[1][c] = Gr[c] * F.x1 + Gr[3 + c] * F.y1 + Gr[6 + c] * F.z1;
+            RB[2][c] = Gr[c] * F.x2 + Gr[3 + c] * F.y2 + Gr[6 + c] * F.z2;
+        }
+        const float t0 = pe0 + P.Gi_t[0] * F.x0 + P.Gi_t[1] * F.y0 + P.Gi_t[2] * F.z0;
+        const float t1 = pe1 + P.Gi_t[0] * F.x1 + P.Gi_t[1] * F.y1 + P.Gi_t[2] * F.z1;
+        const float t2 = pe2 + P.Gi_t[0] * F.x2 + P.Gi_t[1] * F.y2 + P.Gi_t[2] * F.z2;
+        float e[6];
+        e[0] = tx - t0;
+        e[1] = ty - t1;
+        e[2] = tz - t2;
+        if (kind == 0) {
+            // (R_B e_z) x e_z
+            e[3] = RB[1][2];
+            e[4] = -RB[0][2];
+            e[5] = 0.f;
+        } else {
+            // 1/2 sum_c (R_B e_c) x (Rz(yaw) e_c)
+            const float R0[3] = {cy, sy, 0.f}, R1[3] = {-sy, cy, 0.f};
+            float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+            w0 += RB[1][0] * R0[2] - RB[2][0] * R0[1];
+            w1 += RB[2][0] * R0[0] - RB[0][0] * R0[2];
+            w2 += RB[0][0] * R0[1] - RB[1][0] * R0[0];
+            w0 += RB[1][1] * R1[2] - RB[2][1] * R1[1];
+            w1 += RB[2][1] * R1[0] - RB[0][1] * R1[2];
+            w2 += RB[0][1] * R1[1] - RB[1][1] * R1[0];
+            w0 += RB[1][2];   // (R_B e_z) x e_z
+            w1 += -RB[0][2];
+            e[3] = 0.5f * w0;
+            e[4] = 0.5f * w1;
+            e[5] = 0.5f * w2;
+        }
+        // A = J J^T + lambda^2 I, J column j = (z x (t_B - o), z)
+        float A[6][6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A[r][c] = (r == c) ? lam2 : 0.f;
+        float J[NJ][6];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const float r0 = t0 - ax[j][0], r1 = t1 - ax[j][1], r2 = t2 - ax[j][2];
+            const float z0 = ax[j][3], z1 = ax[j][4], z2 = ax[j][5];
+            J[j][0] = z1 * r2 - z2 * r1;
+            J[j][1] = z2 * r0 - z0 * r2;
+            J[j][2] = z0 * r1 - z1 * r0;
+            J[j][3] = z0;
+            J[j][4] = z1;
+            J[j][5] = z2;
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c <= r; ++c) A[r][c] += J[j][r] * J[j][c];
+        }
+        // Cholesky A = L L^T (lower), then L L^T y = e
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float s = A[c][c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) s -= A[c][k] * A[c][k];
+            const float d = sqrtf(fmaxf(s, 1e-30f));
+            A[c][c] = d;
+            const float inv = 1.f / d;
+#pragma unroll
+            for (int r = c + 1; r < 6; ++r) {
+                float t = A[r][c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) t -= A[r][k] * A[c][k];
+                A[r][c] = t * inv;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            float t = e[r];
+#pragma unroll
+            for (int k = 0; k < r; ++k) t -= A[r][k] * e[k];
+            e[r] = t / A[r][r];
+        }
+#pragma unroll
+        for (int r = 5; r >= 0; --r) {
+            float t = e[r];
+#pragma unroll
+            for (int k = r + 1; k < 6; ++k) t -= A[k][r] * e[k];
+            e[r] = t / A[r][r];
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            float dq = 0.f;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) dq += J[j][r] * e[r];
+            q[j] = fminf(fmaxf(q[j] + dq, P.lo[j]), P.hi[j]);
+        }
+    }
+}
+
+__global__ void k_ik_iterate(KProb P, int kind, int n, const float *target, float *qio, int iters)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n) return;
+    float q[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) q[j] = qio[(size_t)gid * NJ + j];
+    const float *t = target + (size_t)gid * 4;
+    ik_run(P, kind, t[0], t[1], t[2], t[3], q, iters);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qio[(size_t)gid * NJ + j] = q[j];
+}
+
+__global__ void k_ik_lift(KProb P, int nP, const float *pose, uint64_t seed, int iters, float *qg, float *qp)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nP * P.B) return;
+    const int p = gid / P.B, b = gid % P.B;
+    float u[8];
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b), 0, 2u, u);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b + 1), 0, 2u, u + 4);
+    float q[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        q[j] = fminf(fmaxf(P.q_home[j] + P.ik_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
+    const float4 I = P.blk_init[2 * b];
+    ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qg[(size_t)gid * NJ + j] = q[j];
+    const float *t = pose + (size_t)gid * 4;
+    ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qp[(size_t)gid * NJ + j] = q[j];
+}
+
+__global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q)
+{
+    const int B = P.B, NS = 2 * B;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nP * NS * W) return;
+    const int w = gid % W, s = (gid / W) % NS, p = gid / (W * NS);
+    const int b = s >> 1;
+    float qa[NJ], qb[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        if (s & 1) {
+            qa[j] = qg[((size_t)p * B + b) * NJ + j];
+            qb[j] = qp[((size_t)p * B + b) * NJ + j];
+        } else {
+            qa[j] = b == 0 ? fminf(fmaxf(P.q_home[j], P.lo[j]), P.hi[j]) : qp[((size_t)p * B + b - 1) * NJ + j];
+            qb[j] = qg[((size_t)p * B + b) * NJ + j];
+        }
+    }
+    float u[8];
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), 0, 3u, u);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), 0, 3u, u + 4);
+    const int m = (W - 1) / 2;
+    float *o = q + (size_t)gid * NJ;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const float qm = fminf(fmaxf(0.5f * (qa[j] + qb[j]) + P.mid_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
+        float v;
+        if (w == 0)
+            v = qa[j];
+        else if (w == W - 1)
+            v = qb[j];
+        else if (w <= m)
+            v = qa[j] + ((float)w / (float)m) * (qm - qa[j]);
+        else
+            v = qm + ((float)(w - m) / (float)(W - 1 - m)) * (qb[j] - qm);
+        o[j] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Solve glue
+// ------------------------------------------------------------------------------------
+// Commit a stage-1 round: if no earlier round committed and this one has satisfying
+// particles (or is the last), its particles in satisfying-first order become the stage-2
+// placements (z at the slot height).  info: [0] stage-1 satisfying count, [1] rounds.
+__global__ __launch_bounds__(1024) void k_commit_stage1(KProb P, int M, int round, int last, const float *xs,
+                                                        const int32_t *order, const int32_t *nsat, float *pose,
+                                                        int *done, int32_t *info)
+{
+    __shared__ int s_go;
+    if (threadIdx.x == 0) s_go = (*done == 0) && (*nsat > 0 || last);
+    __syncthreads();
+    if (!s_go) return;
+    const int B = P.B;
+    for (int e = threadIdx.x; e < M * B; e += blockDim.x) {
+        const int m = e / B, b = e % B;
+        const float *x = xs + ((size_t)order[m] * B + b) * 3;
+        float *o = pose + ((size_t)m * B + b) * 4;
+        o[0] = x[0];
+        o[1] = x[1];
+        o[2] = P.zstar[b];
+        o[3] = x[2];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *done = 1;
+        info[0] = *nsat;
+        info[1] = round + 1;
+    }
+}
+
+__global__ void k_fixed_poses(KProb P, int M, float *pose, int32_t *info)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) {
+        info[0] = -1;
+        info[1] = 0;
+    }
+    if (gid >= M * P.B) return;
+    const int b = gid % P.B;
+    const float4 g = P.goal[2 * b];
+    float *o = pose + (size_t)gid * 4;
+    o[0] = g.x;
+    o[1] = g.y;
+    o[2] = g.z;
+    o[3] = g.w;
+}
+
+// Best particle (first in satisfying-first order): copy it out, path length.
+// info: [2] n_sat, [3] best; finfo: [0] viol, [1] cost, [2] length
+__global__ __launch_bounds__(1024) void k_finalize(KProb P, int M, int W, const float *q, const float *pose,
+                                                   const float *cost, const float *viol, const int32_t *order,
+                                                   const int32_t *nsat, float *best_q, float *best_pose, int32_t *info,
+                                                   float *finfo)
+{
+    __shared__ float s_len[16];
+    const int B = P.B, NS = 2 * B, tid = threadIdx.x;
+    const int best = order[0];
+    const float *qb = q + (size_t)best * NS * W * NJ;
+    for (int e = tid; e < NS * W * NJ; e += blockDim.x) best_q[e] = qb[e];
+    if (tid < 4 * B) best_pose[tid] = pose[(size_t)best * 4 * B + tid];
+    float len = 0.f;
+    for (int e = tid; e < NS * W; e += blockDim.x) {
+        const int w = e % W;
+        if (w == W - 1) continue;
+        float ss = 0.f;
+        for (int j = 0; j < NJ; ++j) {
+            const float d = qb[(e + 1) * NJ + j] - qb[e * NJ + j];
+            ss += d * d;
+        }
+        len += sqrtf(ss);
+    }
+    len = wave_sum(len);
+    if ((tid & 63) == 0) s_len[tid >> 6] = len;
+    __syncthreads();
+    if (tid == 0) {
+        float L = 0.f;
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) L += s_len[wv];
+        info[2] = *nsat;
+        info[3] = best;
+        finfo[0] = viol[best];
+        finfo[1] = cost[best];
+        finfo[2] = L;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+static int lcm_int(int a, int b)
+{
+    int x = a, y = b;
+    while (y) {
+        const int t = x % y;
+        x = y;
+        y = t;
+    }
+    return a / x * b;
+}
+
+hipError_t launch_sample(const KProb &P, int N, uint64_t seed, int round, float *x, const int *skip, hipStream_t st)
+{
+    const int n = N * P.B;
+    hipLaunchKernelGGL(k_sample, dim3((n + 255) / 256), dim3(256), 0, st, P, N, seed, round, x, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const KProb &P, int n, const float *x_in, const int32_t *idx, float *x_out, int k_begin,
+                        int k_end, int eval_phase, float *cost, float *viol, float *gx, const int *skip, hipStream_t st)
+{
+    const int per = 8 * P.B, threads = lcm_int(per, 64), ppw = threads / per;
+    hipLaunchKernelGGL(k_place, dim3((n + ppw - 1) / ppw), dim3(threads), 0, st, P, n, x_in, idx, x_out, k_begin,
+                       k_end, eval_phase, cost, viol, gx, skip);
+    return hipGetLastError();
+}
+
+int traj_threads(int B, int W) { return ((2 * B * W + 63) / 64) * 64; }
+
+template <int CH>
+static hipError_t launch_traj_ch(const KProb &P, int mode, const TrajArgs &a, hipStream_t st)
+{
+    const int threads = traj_threads(P.B, a.W);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_traj<0, CH>), dim3(a.P), dim3(threads), 0, st, P, a);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_traj<1, CH>), dim3(a.P), dim3(threads), 0, st, P, a);
+    else
+        hipLaunchKernelGGL((k_traj<2, CH>), dim3(a.P), dim3(threads), (size_t)2 * NJ * threads * sizeof(float), st,
+                           P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st)
+{
+    // the sphere table is padded so that every link holds a multiple of P.chunk spheres
+    switch (P.chunk) {
+    case 4: return launch_traj_ch<4>(P, mode, a, st);
+    case 6: return launch_traj_ch<6>(P, mode, a, st);
+    case 7: return launch_traj_ch<7>(P, mode, a, st);
+    case 8: return launch_traj_ch<8>(P, mode, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
+    if (e != hipSuccess) return e;
+#define SPASM_TRAJ_ATTR(CH)                                                                                      \
+    e = hipFuncSetAttribute((const void *)k_traj<2, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
+    if (e != hipSuccess) return e;
+    SPASM_TRAJ_ATTR(4)
+    SPASM_TRAJ_ATTR(6)
+    SPASM_TRAJ_ATTR(7)
+    SPASM_TRAJ_ATTR(8)
+#undef SPASM_TRAJ_ATTR
+    return hipSuccess;
+}
+
+hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *viol, float eps, int M,
+                            int32_t *out_idx, int32_t *out_count, const int *skip, hipStream_t st)
+{
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    const size_t shm = (size_t)npow * sizeof(unsigned long long);
+    hipLaunchKernelGGL(k_sort, dim3(1), dim3(1024), shm, st, kind, n, cost, viol, eps, M, out_idx, out_count, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_ik_iterate(const KProb &P, int kind, int n, const float *target, float *q, int iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ik_iterate, dim3((n + 127) / 128), dim3(128), 0, st, P, kind, n, target, q, iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t seed, int iters, float *qg, float *qp,
+                          hipStream_t st)
+{
+    const int n = nP * P.B;
+    hipLaunchKernelGGL(k_ik_lift, dim3((n + 127) / 128), dim3(128), 0, st, P, nP, pose, seed, iters, qg, qp);
+    return hipGetLastError();
+}
+
+hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q,
+                            hipStream_t st)
+{
+    const int n = nP * 2 * P.B * W;
+    hipLaunchKernelGGL(k_traj_init, dim3((n + 255) / 256), dim3(256), 0, st, P, nP, W, qg, qp, seed, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit_stage1(const KProb &P, int M, int round, int last_round, const float *xs,
+                                const int32_t *order, const int32_t *nsat, float *pose, int *done, int32_t *info,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_commit_stage1, dim3(1), dim3(1024), 0, st, P, M, round, last_round, xs, order, nsat, pose,
+                       done, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixed_poses(const KProb &P, int M, float *pose, int32_t *info, hipStream_t st)
+{
+    const int n = M * P.B;
+    hipLaunchKernelGGL(k_fixed_poses, dim3((n + 255) / 256), dim3(256), 0, st, P, M, pose, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const KProb &P, int M, int W, const float *q, const float *pose, const float *cost,
+                           const float *viol, const int32_t *order, const int32_t *nsat, float *best_q,
+                           float *best_pose, int32_t *info, float *finfo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, P, M, W, q, pose, cost, viol, order, nsat, best_q,
+                       best_pose, info, finfo);
+    return hipGetLastError();
+}
+
+}  // namespace spasm

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spasm {
+
+constexpr int NJ = 7;           // joints of the serial chain
+constexpr int MAX_B = 16;       // blocks per problem
+constexpr int MAX_THREADS = 1024;
+constexpr int MAX_SORT = 16384; // single-workgroup sort capacity (LDS bound)
+
+// Problem constants passed BY VALUE to every kernel: they land in the kernel-argument
+// segment and are read into scalar registers, so every lane of a wave shares one copy.
+// Arrays live in device memory and are indexed with wave-uniform indices (scalar loads).
+struct KProb {
+    const float4 *sph;       // [S] link-frame centre xyz, radius; sorted by link
+    const float4 *box;       // [O][2] (cx, cy, cz, 0), (hx, hy, hz, 0)
+    const float4 *blk_init;  // [B][2] (x, y, z, yaw), (cos yaw, sin yaw, 0, 0)
+    const float4 *goal;      // [B][2] same layout (fixed goals)
+    int B, S, O, mode;
+    int chunk;               // spheres tested per box fetch (4, 6, 7 or 8); links padded to it
+    int link_start[8];       // spheres of link k are [link_start[k-1], link_start[k])
+    float a[NJ], d[NJ], ca[NJ], sa[NJ], lo[NJ], hi[NJ], q_home[NJ];
+    float tool_d, h, half, r_blk, sph_off;
+    float samp_x0, samp_xs, samp_y0, samp_ys;      // sample: x = x0 + xs * u
+    float clamp_xl, clamp_xh, clamp_yl, clamp_yh;  // stage-1 clamp box
+    float zstar[MAX_B];      // target centre height of block b
+    float Gi_R[9], Gi_t[3];  // G^-1 (row-major rotation, translation)
+    float w[9];              // stable height coll start tie arm block lim smooth
+    int k_lin1, k_quad1;
+    float eta1, alpha1;
+    float eta2, alpha2, beta1, beta2, adam_eps;
+    int ik_iters;
+    float ik_lambda, ik_noise, mid_noise, sat_eps;
+};
+
+enum { W_STABLE = 0, W_HEIGHT, W_COLL, W_START, W_TIE, W_ARM, W_BLOCK, W_LIM, W_SMOOTH };
+
+// ---- launchers (kernels.hip).  All enqueue on `st` and return the launch status. ----
+// `skip` (nullable, device int): when *skip != 0 the kernel returns immediately; used for
+// the device-side stage-1 retry rounds.
+hipError_t launch_sample(const KProb &P, int N, uint64_t seed, int round, float *x,
+                         const int *skip, hipStream_t st);
+
+// Stage-1 placement kernel: optional gather (x_in rows idx[p]), steps k_begin..k_end-1 of
+// gradient descent, then an evaluation at `eval_phase` writing cost/viol/grad.
+hipError_t launch_place(const KProb &P, int n, const float *x_in, const int32_t *idx, float *x_out,
+                        int k_begin, int k_end, int eval_phase, float *cost, float *viol, float *gx,
+                        const int *skip, hipStream_t st);
+
+struct TrajArgs {
+    int P, W, phase;
+    const float *q_in;
+    const float *pose_in;
+    float *q_out;       // optimise: final trajectory (may alias q_in)
+    float *pose_out;
+    float *opt;         // optimise: Adam moments in/out, nullable (zeros, not written)
+    int k_begin, k_end, k_lin2;
+    const float *gout;  // adjoint scale per particle (nullable)
+    float *cost, *viol; // nullable
+    float *gq, *gpose;  // nullable
+};
+// mode 0: cost only, 1: cost + gradient (scaled by gout if given), 2: optimise
+hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st);
+int traj_threads(int B, int W);
+// raise the dynamic-LDS ceilings of the sort and optimise kernels
+hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes);
+
+hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *viol, float eps,
+                            int M, int32_t *out_idx, int32_t *out_count, const int *skip,
+                            hipStream_t st);
+
+hipError_t launch_ik_iterate(const KProb &P, int kind, int n, const float *target, float *q,
+                             int iters, hipStream_t st);
+hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t seed, int iters,
+                          float *qg, float *qp, hipStream_t st);
+hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp,
+                            uint64_t seed, float *q, hipStream_t st);
+
+// solve glue
+hipError_t launch_commit_stage1(const KProb &P, int M, int round, int last_round, const float *xs,
+                                const int32_t *order, const int32_t *nsat, float *pose, int *done,
+                                int32_t *info, hipStream_t st);
+hipError_t launch_fixed_poses(const KProb &P, int M, float *pose, int32_t *info, hipStream_t st);
+hipError_t launch_finalize(const KProb &P, int M, int W, const float *q, const float *pose,
+                           const float *cost, const float *viol, const int32_t *order,
+                           const int32_t *nsat, float *best_q, float *best_pose, int32_t *info,
+                           float *finfo, hipStream_t st);
+
+}  // namespace spasm

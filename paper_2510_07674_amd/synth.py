@@ -129,8 +129,10 @@ def _chain(rng: np.random.Generator):
     alpha = np.concatenate([rng.choice(np.array([-math.pi / 2, math.pi / 2]), N_JOINTS - 1),
                             rng.choice(np.array([-math.pi / 2, 0.0, math.pi / 2]), 1)])
     dh = np.stack([a, d, alpha], axis=1)
-    lo = np.full(N_JOINTS, -2.8)
-    hi = np.full(N_JOINTS, 2.8)
+    # limits rounded to FP32-representable values: both precisions then compare the same
+    # numbers, so the limit hinges switch at the same configuration
+    lo = np.full(N_JOINTS, float(np.float32(-2.8)))
+    hi = np.full(N_JOINTS, float(np.float32(2.8)))
     return dh, lo, hi
 
 

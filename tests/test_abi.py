@@ -1,0 +1,129 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the header
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "spasm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spasm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("spasm_problem_create", "spasm_problem_destroy", "spasm_sample", "spasm_cost_grad",
+              "spasm_cost_adjoint", "spasm_optimize", "spasm_select_topm", "spasm_order", "spasm_ik_iterate",
+              "spasm_ik_lift", "spasm_traj_init", "spasm_solve", "spasm_solve_workspace", "spasm_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(_declared()) == set(spasm.SYMBOLS)
+
+
+def _problem_args(prob, params):
+    from paper_2510_07674_amd import spasm
+    chain = spasm.chain_desc(prob)
+    pr = spasm.params_desc(params)
+    init = np.ascontiguousarray(prob.block_init, dtype=np.float64)
+    goal = np.ascontiguousarray(np.nan_to_num(prob.goal), dtype=np.float64)
+    sk = spasm.SkeletonDesc()
+    sk.n_blocks, sk.mode = prob.B, prob.mode
+    sk.block_edge, sk.block_margin = prob.h, prob.block_margin
+    sk.block_init = init.ctypes.data_as(ctypes.c_void_p)
+    sk.goal = goal.ctypes.data_as(ctypes.c_void_p)
+    sk.grasp[:] = list(np.asarray(prob.grasp, float).ravel())
+    sk.region[:] = list(prob.table)
+    link = np.ascontiguousarray(prob.sph_link, np.int32)
+    cen = np.ascontiguousarray(prob.sph_c, np.float64)
+    rad = np.ascontiguousarray(prob.sph_r, np.float64)
+    boxes = np.ascontiguousarray(prob.boxes, np.float64)
+    return dict(chain=chain, pr=pr, sk=sk, link=link, cen=cen, rad=rad, boxes=boxes, keep=(init, goal))
+
+
+def _create(a, n_sph=None, n_obs=None):
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    h = ctypes.c_void_p()
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    rc = L.spasm_problem_create(ctypes.byref(a["chain"]), len(a["rad"]) if n_sph is None else n_sph,
+                                vp(a["link"]), vp(a["cen"]), vp(a["rad"]),
+                                len(a["boxes"]) if n_obs is None else n_obs, vp(a["boxes"]), ctypes.byref(a["sk"]),
+                                ctypes.byref(a["pr"]), ctypes.byref(h))
+    return rc, L.spasm_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,code", [
+    ("nan_dh", -1), ("bad_link", -1), ("link_order", -1), ("neg_radius", -1), ("neg_half", -1),
+    ("too_many_blocks", -4), ("bad_mode", -1), ("bad_grasp", -1), ("neg_weight", -1), ("bad_beta", -1),
+    ("small_region", -1), ("neg_count", -1),
+])
+def test_problem_create_rejects(mutate, code):
+    from paper_2510_07674_amd import synth
+    prob, params, _ = synth.config("tower4", 0)
+    a = _problem_args(prob, params)
+    n_sph = None
+    if mutate == "nan_dh":
+        a["chain"].dh[4] = math.nan
+    elif mutate == "bad_link":
+        a["link"][3] = 9
+    elif mutate == "link_order":
+        a["link"][0] = 7
+    elif mutate == "neg_radius":
+        a["rad"][2] = -0.01
+    elif mutate == "neg_half":
+        a["boxes"][1, 4] = -0.1
+    elif mutate == "too_many_blocks":
+        a["sk"].n_blocks = 17
+    elif mutate == "bad_mode":
+        a["sk"].mode = 5
+    elif mutate == "bad_grasp":
+        a["sk"].grasp[0] = 2.0
+    elif mutate == "neg_weight":
+        a["pr"].w[5] = -1.0
+    elif mutate == "bad_beta":
+        a["pr"].beta2 = 1.0
+    elif mutate == "small_region":
+        a["sk"].region[1] = a["sk"].region[0] + 0.01
+    elif mutate == "neg_count":
+        n_sph = -1
+    rc, msg = _create(a, n_sph=n_sph)
+    assert rc == code and msg
+
+
+def test_selection_size_checks():
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    assert L.spasm_select_topm(0, None, 1, None, None) == -4
+    assert L.spasm_select_topm(20000, None, 1, None, None) == -4
+    assert L.spasm_select_topm(100, None, 101, None, None) == -1
+    assert L.spasm_order(0, None, None, 1e-3, None, None, None) == -4
+    assert "outside" in L.spasm_last_error().decode()
+
+
+def test_null_problem_is_rejected():
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    assert L.spasm_sample(None, 10, 0, 0, None, None) == -1
+    assert L.spasm_cost_grad(None, 2, 0, 1, 16, None, None, None, None, None, None, None) == -1
+    assert L.spasm_optimize(None, 2, 1, 16, None, None, None, 1, 2, 1, None, None, None) == -1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2510_07674_amd import spasm
+    monkeypatch.setattr(spasm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(spasm, "_lib", None)
+    with pytest.raises(spasm.SpasmError):
+        spasm.load()

@@ -1,0 +1,478 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs (FP32 inputs widened for the oracle).  Per particle and per waypoint slot:
+
+    |c32 - c64| <= 1e-4 |c64| + 1e-6
+    ||g32 - g64|| <= 1e-4 ||g64|| + f
+
+The floor f is what FP32 can resolve: 1e-6 for unit-magnitude gradient terms (positions
+~1 m, ulp(1) = 1.2e-7, tens of accumulated terms), plus 2 w EPS_POS for the squared
+grasp and tie residuals of weight w, whose residual r is a difference of ~1 m positions
+known to EPS_POS = 1e-6 m after forward kinematics in FP32 (gradient 2 w r J, lever
+|J| <= 1 m).  Per-particle floors are the L2 norm of the slot floors (Minkowski).
+Waypoints/particles whose oracle kink margin is below 1e-5 m are excluded: there a
+penalty switches on or changes face, and FP32 position noise may decide differently;
+the excluded fraction is bounded.  Integer results (top-M, order) are compared bit for
+bit, with both sides sorting the same FP32 keys.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2510_07674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS, KINK = 1e-4, 1e-6, 1e-5
+EPS_POS = 1e-6
+
+
+def slot_floor(pr, NS, W):
+    f = np.full((NS, W), ABS)
+    f[1::2, 0] += 2 * pr.w_start * EPS_POS
+    f[1::2, W - 1] += 2 * pr.w_tie * EPS_POS
+    return f
+
+
+def pose_floor(pr):
+    return ABS + 2 * pr.w_tie * EPS_POS
+
+
+@pytest.fixture(scope="module")
+def sp():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a HIP device")
+    from paper_2510_07674_amd import spasm
+    spasm.load()
+    return spasm
+
+
+def T(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def N(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def f32(a):
+    """Round to FP32 and widen: both sides see the same input values."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def report(name, **kw):
+    print(f"[parity] {name}: " + ", ".join(f"{k}={v:.3g}" if isinstance(v, float) else f"{k}={v}"
+                                           for k, v in kw.items()), flush=True)
+
+
+def check_cost(name, c32, c64, v32, v64):
+    ec = np.abs(c32 - c64) / (REL * np.abs(c64) + ABS)
+    ev = np.abs(v32 - v64) / (REL * np.abs(v64) + 10 * ABS)
+    report(name + " cost", worst_ratio=float(ec.max()), max_rel=float(np.max(np.abs(c32 - c64) / np.maximum(np.abs(c64), 1e-12))))
+    assert np.all(ec <= 1.0), (name, np.argmax(ec), c32[np.argmax(ec)], c64[np.argmax(ec)])
+    assert np.all(ev <= 1.0), (name, np.argmax(ev), v32[np.argmax(ev)], v64[np.argmax(ev)])
+
+
+def check_grad(name, g32, g64, keep, floor=ABS):
+    """g: [P, ...] per particle; keep: bool mask over g[..., 0] excluding near-kink
+    entries; floor: absolute floor per entry of that mask (scalar or array)."""
+    P = g32.shape[0]
+    floor = np.broadcast_to(floor, keep.shape[1:])
+    worst = 0.0
+    for p in range(P):
+        k = keep[p]
+        a = g32[p][k].ravel()
+        b = g64[p][k].ravel()
+        if b.size == 0:
+            continue
+        err = np.linalg.norm(a - b)
+        ratio = err / (REL * np.linalg.norm(b) + np.linalg.norm(floor[k]))
+        worst = max(worst, ratio)
+        assert ratio <= 1.0, (name, p, err, np.linalg.norm(b))
+    report(name + " grad", worst_ratio=worst, kept=float(np.mean(keep)))
+
+
+# --------------------------------------------------------------------------- sampling
+@pytest.mark.parametrize("name", ["tower4", "tower10"])
+def test_sample_matches_oracle(sp, orc, name):
+    prob, pr, _ = synth.config(name, 1)
+    dev = sp.Problem(prob, pr)
+    x32 = N(dev.sample(3000, seed=11, rnd=2))
+    x64 = orc.Oracle(prob, pr).sample(3000, 11, 2)
+    err = np.abs(x32 - x64).max()
+    report("sample " + name, max_abs=float(err))
+    assert err <= 1e-6
+
+
+# ------------------------------------------------------------------- stage-1 cost
+@pytest.mark.parametrize("name", ["tower4", "tower10"])
+@pytest.mark.parametrize("phase", [0, 1])
+def test_place_cost_parity(sp, orc, name, phase):
+    rng = np.random.default_rng(100 + phase)
+    prob, pr, _ = synth.config(name, 2)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    x = np.concatenate([synth.clustered_placements(rng, prob, 700), synth.random_placements(rng, prob, 300)])
+    x = f32(x)
+    c32, v32, g32 = (N(t) for t in dev.place_cost(T(x), phase))
+    c64, v64, g64, kink = o.place_cost(x, phase)
+    check_cost(f"place {name} ph{phase}", c32, c64, v32, v64)
+    keep = np.broadcast_to((kink >= KINK)[:, None], g64.shape[:2])
+    assert keep.mean() > 0.8
+    check_grad(f"place {name} ph{phase}", g32, g64, keep)
+    # cost-only launch agrees with the cost+gradient launch
+    c0, v0, _ = (N(t) if t is not None else None for t in dev.place_cost(T(x), phase, grad=False))
+    assert np.allclose(c0, c32, rtol=1e-6, atol=1e-7) and np.allclose(v0, v32, rtol=1e-6, atol=1e-7)
+
+
+# ------------------------------------------------------------------- stage-2 cost
+def _states(kind, prob, pr, orc, rng, P, W):
+    if kind == "random":
+        return synth.random_states(rng, prob, P, W)
+    # realistic: lifted and seeded by the oracle (FP64), as the solver would start
+    o = orc.Oracle(prob, pr)
+    if prob.mode == synth.MODE_FIXED:
+        pose = np.repeat(prob.goal[None], P, axis=0)
+    else:
+        x = synth.clustered_placements(rng, prob, P, spread=0.01)
+        pose = o.initial_poses(x)
+    qg, qp = o.ik_lift(pose, seed=int(rng.integers(1000)))
+    return o.traj_init(qg, qp, W, seed=int(rng.integers(1000))), pose
+
+
+def _traj_parity(sp, orc, prob, pr, q, pose, label, phases=(0, 1)):
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    q, pose = f32(q), f32(pose)
+    for phase in phases:
+        c32, v32, gq32, gp32 = (N(t) for t in dev.traj_cost(T(q), T(pose), phase))
+        c64, v64, gq64, gp64, sk, pk = o.traj_cost(q, pose, phase)
+        check_cost(f"traj {label} ph{phase}", c32, c64, v32, v64)
+        keep = sk >= KINK
+        # the boundary copies are compared separately per slot, so a kink at either
+        # copy only removes that slot
+        assert keep.mean() > 0.85, keep.mean()
+        fl = slot_floor(pr, q.shape[1], q.shape[2])
+        check_grad(f"traj {label} ph{phase} q", gq32, gq64, keep, fl)
+        # per slot
+        d = np.linalg.norm(gq32 - gq64, axis=-1)
+        lim = REL * np.linalg.norm(gq64, axis=-1) + fl[None]
+        bad = keep & (d > lim)
+        report(f"traj {label} ph{phase} slots", worst_ratio=float(np.max(np.where(keep, d / lim, 0))))
+        assert not bad.any(), np.argwhere(bad)[:5]
+        pkeep = np.broadcast_to((pk >= KINK)[:, None], gp64.shape[:2])
+        check_grad(f"traj {label} ph{phase} pose", gp32, gp64, pkeep, pose_floor(pr))
+        c0, v0, _, _ = dev.traj_cost(T(q), T(pose), phase, grad=False)
+        assert np.allclose(N(c0), c32, rtol=1e-6, atol=1e-6) and np.allclose(N(v0), v32, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("name,W,P,kind", [
+    ("tiny", 16, 48, "random"), ("tiny", 16, 48, "lifted"),
+    ("tower4", 32, 6, "random"), ("tower4", 32, 6, "lifted"),
+    ("tower10", 32, 2, "random"), ("tower10", 32, 3, "lifted"),
+])
+def test_traj_cost_parity(sp, orc, name, W, P, kind):
+    rng = np.random.default_rng(200 + W + P)
+    prob, pr, _ = synth.config(name, 3)
+    q, pose = _states(kind, prob, pr, orc, rng, P, W)
+    _traj_parity(sp, orc, prob, pr, q, pose, f"{name} W{W} {kind}")
+
+
+@pytest.mark.parametrize("B,W", [(3, 16), (1, 4), (2, 8), (5, 64), (16, 32)])
+def test_traj_cost_ragged_shapes(sp, orc, B, W):
+    """Slot counts 2BW that leave a partly idle wave (3x16: 96 lanes), tiny segments,
+    wave-sized segments, and the largest block count."""
+    rng = np.random.default_rng(300 + B * W)
+    prob = synth.make_problem(7, B=B, O=12, S=42)
+    pr = synth.Params()
+    q, pose = _states("lifted" if B <= 5 else "random", prob, pr, orc, rng, 3, W)
+    _traj_parity(sp, orc, prob, pr, q, pose, f"B{B} W{W}", phases=(0,))
+
+
+def test_traj_cost_edge_cases(sp, orc):
+    """No obstacles; a single sphere per link; fixed goals with 3 blocks."""
+    rng = np.random.default_rng(400)
+    prob = synth.make_problem(8, B=2, O=0, S=42)
+    pr = synth.Params()
+    q, pose = synth.random_states(rng, prob, 3, 8)
+    _traj_parity(sp, orc, prob, pr, q, pose, "no obstacles", phases=(0,))
+    prob = synth.make_problem(9, B=2, O=20, S=7)
+    q, pose = synth.random_states(rng, prob, 3, 8)
+    _traj_parity(sp, orc, prob, pr, q, pose, "7 spheres", phases=(1,))
+    prob = synth.make_problem(10, B=3, O=20, S=42, mode=synth.MODE_FIXED)
+    q, pose = synth.random_states(rng, prob, 3, 16)
+    _traj_parity(sp, orc, prob, pr, q, pose, "fixed goals", phases=(0, 1))
+
+
+def test_adjoint_is_scaled_gradient(sp):
+    rng = np.random.default_rng(500)
+    prob, pr, _ = synth.config("tower4", 4)
+    dev = sp.Problem(prob, pr)
+    q, pose = synth.random_states(rng, prob, 16, 32)
+    q, pose = T(q), T(pose)
+    gout = T(rng.normal(size=16))
+    _, _, gq, gp = dev.traj_cost(q, pose, 0)
+    aq, ap = dev.traj_adjoint(q, pose, gout, 0)
+    s = gout.view(16, 1, 1, 1)
+    assert torch.equal(aq, gq * s)
+    assert torch.equal(ap, gp * gout.view(16, 1, 1))
+
+
+def test_autograd_matches_finite_differences(sp, orc):
+    """SpasmCost backward against central differences of the FP64 oracle cost along
+    random directions (h = 1e-6), on 256 particles of the 4-block tower."""
+    rng = np.random.default_rng(600)
+    prob, pr, _ = synth.config("tower4", 5)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    P, W = 256, 4
+    q, pose = synth.random_states(rng, prob, P, W)
+    q, pose = f32(q), f32(pose)
+    tq = T(q).requires_grad_(True)
+    tp = T(pose).requires_grad_(True)
+    cost = sp.SpasmCost.apply(tq, tp, dev, 0)
+    cost.sum().backward()
+    gq, gp = N(tq.grad), N(tp.grad)
+    dq = rng.normal(size=q.shape)
+    dp = rng.normal(size=pose.shape)
+    h = 1e-6
+    fp = o.traj_cost(q + h * dq, pose + h * dp, 0, grad=False)[0]
+    fm = o.traj_cost(q - h * dq, pose - h * dp, 0, grad=False)[0]
+    fd = (fp - fm) / (2 * h)
+    an = np.einsum("pswj,pswj->p", gq, dq) + np.einsum("pbk,pbk->p", gp, dp)
+    scale = np.sqrt(np.einsum("pswj->p", gq ** 2 * dq ** 2) + np.einsum("pbk->p", gp ** 2 * dp ** 2)) + 1.0
+    rel = np.abs(an - fd) / scale
+    report("autograd fd", median=float(np.median(rel)), p95=float(np.percentile(rel, 95)))
+    # a direction that crosses a penalty switch inside +-h disagrees; these are rare
+    assert np.mean(rel < 1e-3) > 0.95
+    c64 = o.traj_cost(q, pose, 0, grad=False)[0]
+    assert np.allclose(N(cost), c64, rtol=1e-4, atol=1e-6)
+
+
+# ---------------------------------------------------------------- selection
+def test_topm_bit_exact(sp, orc):
+    rng = np.random.default_rng(700)
+    for n, m in [(16384, 2048), (4096, 1024), (1000, 999), (1, 1), (3000, 7)]:
+        key = np.round(rng.uniform(0, 1, n), 3).astype(np.float32)  # many ties
+        idx = N(sp.select_topm(T(key), m)).astype(np.int64)
+        ref = orc.Oracle.argsort(key.astype(np.float64))[:m]
+        assert np.array_equal(idx, ref), (n, m)
+
+
+def test_order_bit_exact(sp, orc):
+    rng = np.random.default_rng(701)
+    prob, pr, _ = synth.config("tower4", 0)
+    o = orc.Oracle(prob, pr)
+    for n in (2048, 1024, 37, 16384):
+        cost = np.round(rng.uniform(0, 1, n), 3).astype(np.float32)
+        viol = np.where(rng.uniform(size=n) < 0.3, 0, rng.uniform(0, 2e-3, n)).astype(np.float32)
+        out, ns = sp.order(T(cost), T(viol), pr.sat_eps)
+        ref, nref = o.order(cost.astype(np.float64), viol.astype(np.float64))
+        assert np.array_equal(N(out).astype(np.int64), ref) and int(N(ns)[0]) == nref
+
+
+# ----------------------------------------------------------- updates (teacher forced)
+def test_place_optimize_teacher_forced(sp, orc):
+    rng = np.random.default_rng(800)
+    prob, pr, _ = synth.config("tower4", 6)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    x = T(f32(synth.clustered_placements(rng, prob, 512)))
+    K = pr.k_lin1 + pr.k_quad1
+    for k in range(1, K + 1):
+        xk = N(x)
+        dev.place_optimize(x, k, k + 1)
+        x1 = N(x)
+        phase, lr = o.schedule(k, pr.k_lin1, pr.eta1, pr.alpha1)
+        c, v, g, kink = o.place_cost(xk, phase)
+        ref = o.gd_step(xk, g, lr)
+        keep = kink >= KINK
+        # first order: |dx| <= lr |dg|, with the gradient error bounded per particle
+        gn = np.linalg.norm(g.reshape(g.shape[0], -1), axis=1)[:, None, None]
+        tol = 4 * np.finfo(np.float32).eps * np.abs(xk) + lr * (REL * gn + ABS) + 1e-7
+        bad = (np.abs(x1 - ref) > tol) & keep[:, None, None]
+        assert not bad.any(), (k, np.argwhere(bad)[:3])
+    # a fused multi-step launch equals step-by-step launches bit for bit
+    xa = T(f32(synth.clustered_placements(rng, prob, 256)))
+    xb = xa.clone()
+    dev.place_optimize(xa, 1, K + 1)
+    for k in range(1, K + 1):
+        dev.place_optimize(xb, k, k + 1)
+    assert torch.equal(xa, xb)
+
+
+@pytest.mark.parametrize("name,W,P", [("tiny", 16, 32), ("tower4", 32, 4)])
+def test_traj_optimize_teacher_forced(sp, orc, name, W, P):
+    """Each Adam step from the GPU state: the oracle recomputes the gradient in FP64 and
+    applies its own step to the same state and moments."""
+    rng = np.random.default_rng(900)
+    prob, pr, cfg = synth.config(name, 7)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    q0, pose0 = _states("lifted", prob, pr, orc, rng, P, W)
+    q, pose = T(f32(q0)), T(f32(pose0))
+    K = cfg.K
+    opt = dev.opt_state(P, W)
+    nq = 2 * prob.B * W * 7
+    per = nq + 4 * prob.B
+    worst = 0.0
+    for k in range(1, K + 1):
+        qk, pk, ok = N(q), N(pose), N(opt)
+        dev.traj_optimize(q, pose, opt, k, k + 1, K, want_cost=False)
+        q1, p1 = N(q), N(pose)
+        phase, lr = o.schedule(k, pr.k_lin2(K), pr.eta2, pr.alpha2)
+        _, _, gq, gp, sk, pkk = o.traj_cost(qk, pk, phase)
+        mq = ok[:, :nq].reshape(qk.shape)
+        vq = ok[:, per:per + nq].reshape(qk.shape)
+        mp = ok[:, nq:per].reshape(pk.shape)
+        vp = ok[:, per + nq:].reshape(pk.shape)
+        rq, rp, *_ = o.adam_step(qk, pk, mq, vq, mp, vp, gq, gp, lr, k)
+        # First-order bound of the Adam step's sensitivity to the gradient error dg:
+        # |d step| <= 2 lr dg / (sqrt(v_hat) + eps), dg <= 1e-4 |g_slot| + floor (boundary
+        # copies: both copies' bounds add).  Near-kink slots are skipped.
+        fl = slot_floor(pr, qk.shape[1], W)
+        dg = REL * np.linalg.norm(gq, axis=-1) + fl[None]
+        dgs = dg.copy()
+        dgs[:, :-1, W - 1] += dg[:, 1:, 0]
+        dgs[:, 1:, 0] = dgs[:, :-1, W - 1]
+        gsum = gq.copy()
+        gsum[:, :-1, W - 1] += gq[:, 1:, 0]
+        gsum[:, 1:, 0] = gsum[:, :-1, W - 1]
+        b2 = pr.beta2
+        vhat = (b2 * vq + (1 - b2) * gsum ** 2) / (1 - b2 ** k)
+        ok_c = np.broadcast_to((sk >= KINK)[..., None], qk.shape).copy()
+        ok_c[:, :-1, W - 1] &= (sk[:, 1:, 0] >= KINK)[..., None]
+        ok_c[:, 1:, 0] &= (sk[:, :-1, W - 1] >= KINK)[..., None]
+        tol = 4 * np.finfo(np.float32).eps * np.abs(qk) + 2 * lr * dgs[..., None] / (np.sqrt(vhat) + pr.adam_eps) + 1e-7
+        err = np.abs(q1 - rq)
+        worst = max(worst, float(np.max(np.where(ok_c, err / tol, 0))))
+        assert np.all(err[ok_c] <= tol[ok_c]), (k, np.argwhere(ok_c & (err > tol))[:3])
+        assert np.array_equal(q1[:, :-1, W - 1], q1[:, 1:, 0])  # boundary copies stay equal
+        if prob.mode == 0:
+            gpn = np.linalg.norm(gp.reshape(gp.shape[0], -1), axis=1)[:, None, None]
+            vph = (b2 * vp + (1 - b2) * gp ** 2) / (1 - b2 ** k)
+            tolp = 4 * np.finfo(np.float32).eps * np.abs(pk) + 2 * lr * (REL * gpn + pose_floor(pr)) / (np.sqrt(vph) + pr.adam_eps) + 1e-7
+            keep_p = np.broadcast_to((pkk >= KINK)[:, None, None], pk.shape)
+            assert np.all(np.abs(p1 - rp)[keep_p] <= tolp[keep_p]), k
+        else:
+            assert np.array_equal(p1, pk)
+    report(f"adam {name}", worst_ratio=worst)
+    # fused K-step launch equals step-by-step launches bit for bit
+    qa, pa = T(f32(q0)), T(f32(pose0))
+    qb, pb = qa.clone(), pa.clone()
+    oa, ob = dev.opt_state(P, W), dev.opt_state(P, W)
+    dev.traj_optimize(qa, pa, oa, 1, K + 1, K)
+    for k in range(1, K + 1):
+        dev.traj_optimize(qb, pb, ob, k, k + 1, K, want_cost=False)
+    assert torch.equal(qa, qb) and torch.equal(pa, pb) and torch.equal(oa, ob)
+
+
+# ------------------------------------------------------------------ lift / seeding
+def test_ik_iterate_teacher_forced(sp, orc):
+    rng = np.random.default_rng(1000)
+    prob, pr, _ = synth.config("tower4", 8)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    n = 256
+    q = f32(rng.uniform(-2, 2, (n, 7)))
+    tgt = f32(np.stack([rng.uniform(0.2, 0.55, n), rng.uniform(-0.35, 0.35, n), np.full(n, 0.025),
+                        rng.uniform(-3, 3, n)], 1))
+    for kind in (0, 1):
+        tq = T(q)
+        dev.ik_iterate(kind, T(tgt), tq, 1)
+        g = N(tq)
+        ref = np.stack([o.ik_iterate(kind, tgt[i], q[i], 1) for i in range(n)])
+        # one DLS step solves a 6x6 system with condition number <= (|J|^2 + lambda^2)/lambda^2
+        step = np.linalg.norm(ref - q, axis=1)
+        err = np.linalg.norm(g - ref, axis=1)
+        report(f"ik step kind{kind}", max_rel=float(np.max(err / (step + 1e-6))))
+        assert np.all(err <= 2e-3 * step + 1e-5)
+
+
+def _block_residual(o, prob, q, tgt, kind):
+    F = o.fk(q)
+    R, p = F[8, :9].reshape(3, 3), F[8, 9:]
+    G = prob.grasp
+    RB = R @ G[:, :3].T
+    tB = p + R @ (-G[:, :3].T @ G[:, 3])
+    e = np.linalg.norm(tB - tgt[:3]) + np.linalg.norm(RB[:, 2] - [0, 0, 1])
+    if kind == 1:
+        e += np.linalg.norm(RB[:, 0] - [math.cos(tgt[3]), math.sin(tgt[3]), 0])
+    return e
+
+
+def test_ik_lift_parity(sp, orc):
+    """50-iteration lift: where the FP64 solve converged (residual < 1e-5), the FP32
+    solve reaches the same configuration; elsewhere both are only starting points."""
+    rng = np.random.default_rng(1001)
+    prob, pr, _ = synth.config("tower4", 9)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    P = 64
+    pose = f32(o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.01)))
+    qg32, qp32 = (N(t) for t in dev.ik_lift(T(pose), seed=5))
+    qg64, qp64 = o.ik_lift(pose, seed=5)
+    conv_g = np.array([[_block_residual(o, prob, qg64[p, b], prob.block_init[b], 0) < 1e-5
+                        for b in range(prob.B)] for p in range(P)])
+    conv_p = np.array([[_block_residual(o, prob, qp64[p, b], pose[p, b], 1) < 1e-5
+                        for b in range(prob.B)] for p in range(P)])
+    dg = np.abs(qg32 - qg64).max(-1)
+    dp = np.abs(qp32 - qp64).max(-1)
+    report("ik lift", grasp_conv=float(conv_g.mean()), place_conv=float(conv_p.mean()),
+           grasp_close=float(np.mean(dg[conv_g] < 1e-3)), place_close=float(np.mean(dp[conv_p & conv_g] < 1e-3)))
+    assert conv_g.mean() > 0.5
+    assert np.mean(dg[conv_g] < 1e-3) > 0.95
+    assert np.mean(dp[conv_p & conv_g] < 1e-3) > 0.9
+
+
+def test_traj_init_parity(sp, orc):
+    rng = np.random.default_rng(1100)
+    for name, W in (("tower4", 32), ("tiny", 16)):
+        prob, pr, _ = synth.config(name, 10)
+        dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+        P = 33
+        qg = f32(rng.uniform(-2.5, 2.5, (P, prob.B, 7)))
+        qp = f32(rng.uniform(-2.5, 2.5, (P, prob.B, 7)))
+        q32 = N(dev.traj_init(T(qg), T(qp), W, seed=77))
+        q64 = o.traj_init(qg, qp, W, seed=77)
+        assert np.abs(q32 - q64).max() <= 2e-6
+        assert np.array_equal(q32[:, :-1, W - 1], q32[:, 1:, 0])
+
+
+# ------------------------------------------------------------------ whole method
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_solve_tiny_free_running(sp, orc, seed):
+    prob, pr, cfg = synth.config("tiny", seed)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    res, bq, bp = dev.solve(cfg)
+    ref = o.solve(cfg)
+    vbest = float(ref["viol"][ref["best"]])
+    report(f"solve tiny {seed}", gpu_success=res["success"], gpu_viol=res["viol"], oracle_success=int(ref["success"]),
+           oracle_viol=vbest, ms=res["total_ms"])
+    if abs(vbest - pr.sat_eps) > 1e-5 and abs(res["viol"] - pr.sat_eps) > 1e-5:
+        assert bool(res["success"]) == bool(ref["success"])
+    # the returned particle is consistent with a fresh evaluation of itself
+    c, v, _, _ = dev.traj_cost(bq[None].contiguous(), bp[None].contiguous(), 1, grad=False)
+    assert abs(float(N(v)[0]) - res["viol"]) <= 1e-6 + 1e-5 * res["viol"]
+
+
+def test_solve_tower4_runs_and_is_deterministic(sp):
+    prob, pr, cfg = synth.config("tower4", 0)
+    dev = sp.Problem(prob, pr)
+    r1, q1, p1 = dev.solve(cfg)
+    r2, q2, p2 = dev.solve(cfg)
+    report("solve tower4", success=r1["success"], viol=r1["viol"], stage1_sat=r1["stage1_sat"],
+           rounds=r1["rounds"], ms=r1["total_ms"], s1=r1["stage1_ms"], s2=r1["stage2_ms"])
+    assert torch.equal(q1, q2) and torch.equal(p1, p2)
+    assert r1["viol"] == r2["viol"] and r1["best"] == r2["best"]
+    assert r1["rounds"] >= 1
+
+
+def test_full_size_sampled(sp, orc):
+    """10-block tower at full size (2048 particles x 20 segments x 32 waypoints, 48
+    spheres, 80 boxes) in one launch; the oracle recomputes a sample of particles."""
+    rng = np.random.default_rng(1200)
+    prob, pr, cfg = synth.config("tower10", 11)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    P, W = cfg.M, cfg.W
+    q, pose = synth.random_states(rng, prob, P, W)
+    q, pose = f32(q), f32(pose)
+    c32, v32, gq32, gp32 = (N(t) for t in dev.traj_cost(T(q), T(pose), 0))
+    pick = np.array([0, 777, P - 1])
+    c64, v64, gq64, gp64, sk, pk = o.traj_cost(q[pick], pose[pick], 0)
+    check_cost("full tower10", c32[pick], c64, v32[pick], v64)
+    check_grad("full tower10 q", gq32[pick], gq64, sk >= KINK)
