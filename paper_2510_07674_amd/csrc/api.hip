@@ -254,8 +254,6 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         K.clamp_yl = (float)yl;
         K.clamp_yh = (float)yh;
     }
-    for (int b = 0; b < B; ++b)
-        K.zstar[b] = (float)(skel->mode == SPASM_MODE_TOWER ? (b + 0.5) * h : skel->goal[4 * b + 2]);
     for (int i = 0; i < 3; ++i) {
         for (int j = 0; j < 3; ++j) K.Gi_R[3 * i + j] = (float)skel->grasp[j][i];
         double t = 0.0;

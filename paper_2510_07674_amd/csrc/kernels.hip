@@ -18,8 +18,26 @@ namespace spasm {
 // helpers
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(float x) { return x >= 0.f ? 1.f : -1.f; }
+
+// The problem tables are never written while a kernel runs.  Reading them through the
+// constant address space lets the compiler use scalar loads for wave-uniform indices
+// even after workgroup barriers (which otherwise count as possible writers).
+typedef __attribute__((address_space(4))) const float cfloat;
+__device__ __forceinline__ float4 ldc(const float4 *p, int i)
+{
+    cfloat *q = (cfloat *)(p + i);
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
 __device__ __forceinline__ float phi(int phase, float d) { return phase ? d * d : d; }
 __device__ __forceinline__ float dphi(int phase, float d) { return phase ? 2.f * d : 1.f; }
+
+// Target centre height of block b (tower slot or fixed goal).  Computed, not read from
+// an array in the kernel argument: a per-lane index into the by-value argument would
+// force the whole argument into per-lane scratch memory.
+__device__ __forceinline__ float zstar(const KProb &P, int b)
+{
+    return P.mode == 0 ? ((float)b + 0.5f) * P.h : ldc(P.goal, 2 * b).z;
+}
 
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -143,7 +161,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
                                               bool act, float &cost, float &viol, float (&wf)[3], float (&wt)[3])
 {
     for (int o = 0; o < P.O; ++o) {
-        const float4 bc = P.box[2 * o], be = P.box[2 * o + 1];
+        const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
         bool hit = false;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
@@ -266,7 +284,7 @@ __device__ __forceinline__ void collide_blocks(const KProb &P, int phase, float 
 // st: LDS pose table of the particle [B][8] = x, y, z, yaw, cos, sin.
 // ------------------------------------------------------------------------------------
 template <bool GRAD>
-__device__ void place_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost, float &viol,
+__device__ __forceinline__ void place_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost, float &viol,
                            float (&g)[4])
 {
     const int B = P.B;
@@ -278,7 +296,7 @@ __device__ void place_lane(const KProb &P, int phase, int i, int k, const float 
     const float dyx = -si * sbx - ci * sby, dyy = ci * sbx - si * sby;  // d c / d yaw
 
     for (int o = 0; o < P.O; ++o) {
-        const float4 bc = P.box[2 * o], be = P.box[2 * o + 1];
+        const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
         const float dx = cx - bc.x, dy = cy - bc.y, dz = cz - bc.z;
         const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
         if (fmaxf(fmaxf(ux, uy), uz) < rb) {
@@ -305,7 +323,7 @@ __device__ void place_lane(const KProb &P, int phase, int i, int k, const float 
             if (tgt == 0) {
                 tx = st[j * 8 + 0]; ty = st[j * 8 + 1]; tz = st[j * 8 + 2]; cs = st[j * 8 + 4]; sn = st[j * 8 + 5];
             } else {
-                const float4 a0 = P.blk_init[2 * j], a1 = P.blk_init[2 * j + 1];
+                const float4 a0 = ldc(P.blk_init, 2 * j), a1 = ldc(P.blk_init, 2 * j + 1);
                 tx = a0.x; ty = a0.y; tz = a0.z; cs = a1.x; sn = a1.y;
             }
             const float dx = cx - tx, dy = cy - ty, dz = cz - tz;
@@ -352,7 +370,7 @@ __device__ void place_lane(const KProb &P, int phase, int i, int k, const float 
     }
     if (k == 0) {
         const float w_h = P.w[W_HEIGHT], w_s = P.w[W_STABLE];
-        const float e = zi - P.zstar[i];
+        const float e = zi - zstar(P, i);
         cost += w_h * e * e;
         viol = fmaxf(viol, fabsf(e));
         if (GRAD) g[2] += 2.f * w_h * e;
@@ -441,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
         sincosf(yaw, &s, &c);
         st[i * 8 + 0] = x;
         st[i * 8 + 1] = y;
-        st[i * 8 + 2] = P.zstar[i];
+        st[i * 8 + 2] = zstar(P, i);
         st[i * 8 + 3] = yaw;
         st[i * 8 + 4] = c;
         st[i * 8 + 5] = s;
@@ -548,7 +566,7 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
     if (GRAD) {
         // evaluate here: sinking it would keep every joint's axis and wrench live
         float t = screw_dot(F, wr);
-        asm volatile("" : "+v"(t));
+        asm("" : "+v"(t));
         g[J] -= t;
     }
     dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
@@ -557,7 +575,7 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
         float cx[CH], cy[CH], cz[CH], r[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const float4 sp = P.sph[s0 + i];
+            const float4 sp = ldc(P.sph, s0 + i);
             cx[i] = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
             cy[i] = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
             cz[i] = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
@@ -636,7 +654,7 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
     // grasp alignment at the first transfer waypoint (C_start: position, roll/pitch)
     if (sl.active && sl.tau == 1 && sl.w == 0) {
         const float w_st = P.w[W_START];
-        const float4 I = P.blk_init[2 * sl.b];
+        const float4 I = ldc(P.blk_init, 2 * sl.b);
         const float rp0 = tb0 - I.x, rp1 = tb1 - I.y, rp2 = tb2 - I.z;
         const float u0 = RB[0][2], u1 = RB[1][2], u2 = RB[2][2];
         const float rz0 = u0, rz1 = u1, rz2 = u2 - 1.f;
@@ -693,7 +711,7 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             qr[j] = q[j];
-            asm volatile("" : "+v"(qr[j]));
+            asm("" : "+v"(qr[j]));
         }
         frame_identity(F);
         links_reverse<0>(P, qr, F, g, wtot);
@@ -822,7 +840,7 @@ __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
         set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3]);
     } else if (tid < 2 * B) {  // blockDim >= 64 >= 2 * MAX_B
         const int b = tid - B;
-        const float4 a0 = P.blk_init[2 * b], a1 = P.blk_init[2 * b + 1];
+        const float4 a0 = ldc(P.blk_init, 2 * b), a1 = ldc(P.blk_init, 2 * b + 1);
         float *pp = s_pose + (MAX_B + b) * 8;
         pp[0] = a0.x;
         pp[1] = a0.y;
@@ -1043,7 +1061,7 @@ __global__ __launch_bounds__(1024) void k_sort(int kind, int n, const float *cos
 // ------------------------------------------------------------------------------------
 // Lift (damped least squares on the block frame) and trajectory seeding.
 // ------------------------------------------------------------------------------------
-__device__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ], int iters)
+__device__ __forceinline__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ], int iters)
 {
     float sy, cy;
     sincosf(tyaw, &sy, &cy);
@@ -1183,7 +1201,7 @@ __global__ void k_ik_lift(KProb P, int nP, const float *pose, uint64_t seed, int
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
         q[j] = fminf(fmaxf(P.q_home[j] + P.ik_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
-    const float4 I = P.blk_init[2 * b];
+    const float4 I = ldc(P.blk_init, 2 * b);
     ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qg[(size_t)gid * NJ + j] = q[j];
@@ -1253,7 +1271,7 @@ __global__ __launch_bounds__(1024) void k_commit_stage1(KProb P, int M, int roun
         float *o = pose + ((size_t)m * B + b) * 4;
         o[0] = x[0];
         o[1] = x[1];
-        o[2] = P.zstar[b];
+        o[2] = zstar(P, b);
         o[3] = x[2];
     }
     __syncthreads();
@@ -1273,7 +1291,7 @@ __global__ void k_fixed_poses(KProb P, int M, float *pose, int32_t *info)
     }
     if (gid >= M * P.B) return;
     const int b = gid % P.B;
-    const float4 g = P.goal[2 * b];
+    const float4 g = ldc(P.goal, 2 * b);
     float *o = pose + (size_t)gid * 4;
     o[0] = g.x;
     o[1] = g.y;

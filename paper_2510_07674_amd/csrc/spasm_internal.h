@@ -26,7 +26,6 @@ struct KProb {
     float tool_d, h, half, r_blk, sph_off;
     float samp_x0, samp_xs, samp_y0, samp_ys;      // sample: x = x0 + xs * u
     float clamp_xl, clamp_xh, clamp_yl, clamp_yh;  // stage-1 clamp box
-    float zstar[MAX_B];      // target centre height of block b
     float Gi_R[9], Gi_t[3];  // G^-1 (row-major rotation, translation)
     float w[9];              // stable height coll start tie arm block lim smooth
     int k_lin1, k_quad1;

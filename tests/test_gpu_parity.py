@@ -397,8 +397,11 @@ def _block_residual(o, prob, q, tgt, kind):
 
 
 def test_ik_lift_parity(sp, orc):
-    """50-iteration lift: where the FP64 solve converged (residual < 1e-5), the FP32
-    solve reaches the same configuration; elsewhere both are only starting points."""
+    """50-iteration lift.  The chain is redundant (7 joints, 5 or 6 constraints) and the
+    limit clamp is discontinuous, so FP32 and FP64 may converge to different valid
+    configurations; single iterations are compared in test_ik_iterate_teacher_forced.
+    Here: the FP32 solutions reach their targets (residual measured in FP64) at the same
+    rate as the FP64 solves, and agree with them where both converged to one basin."""
     rng = np.random.default_rng(1001)
     prob, pr, _ = synth.config("tower4", 9)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
@@ -406,17 +409,25 @@ def test_ik_lift_parity(sp, orc):
     pose = f32(o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.01)))
     qg32, qp32 = (N(t) for t in dev.ik_lift(T(pose), seed=5))
     qg64, qp64 = o.ik_lift(pose, seed=5)
-    conv_g = np.array([[_block_residual(o, prob, qg64[p, b], prob.block_init[b], 0) < 1e-5
-                        for b in range(prob.B)] for p in range(P)])
-    conv_p = np.array([[_block_residual(o, prob, qp64[p, b], pose[p, b], 1) < 1e-5
-                        for b in range(prob.B)] for p in range(P)])
-    dg = np.abs(qg32 - qg64).max(-1)
-    dp = np.abs(qp32 - qp64).max(-1)
-    report("ik lift", grasp_conv=float(conv_g.mean()), place_conv=float(conv_p.mean()),
-           grasp_close=float(np.mean(dg[conv_g] < 1e-3)), place_close=float(np.mean(dp[conv_p & conv_g] < 1e-3)))
-    assert conv_g.mean() > 0.5
-    assert np.mean(dg[conv_g] < 1e-3) > 0.95
-    assert np.mean(dp[conv_p & conv_g] < 1e-3) > 0.9
+
+    def residuals(qg, qp):
+        rg = np.array([[_block_residual(o, prob, qg[p, b], prob.block_init[b], 0) for b in range(prob.B)]
+                       for p in range(P)])
+        rp = np.array([[_block_residual(o, prob, qp[p, b], pose[p, b], 1) for b in range(prob.B)]
+                       for p in range(P)])
+        return rg, rp
+
+    rg64, rp64 = residuals(qg64, qp64)
+    rg32, rp32 = residuals(qg32, qp32)
+    cg64, cp64 = rg64 < 1e-5, rp64 < 1e-5
+    cg32, cp32 = rg32 < 1e-4, rp32 < 1e-4
+    same_g = np.abs(qg32 - qg64).max(-1) < 1e-3
+    report("ik lift", grasp_conv64=float(cg64.mean()), grasp_conv32=float(cg32.mean()),
+           place_conv64=float(cp64.mean()), place_conv32=float(cp32.mean()),
+           same_basin=float(same_g[cg64 & cg32].mean()))
+    assert cg64.mean() > 0.5
+    assert abs(cg32.mean() - cg64.mean()) <= 0.1 and abs(cp32.mean() - cp64.mean()) <= 0.1
+    assert same_g[cg64 & cg32].mean() > 0.7
 
 
 def test_traj_init_parity(sp, orc):
