@@ -71,7 +71,20 @@ def main():
     ap.add_argument("--workload", default="tower4")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (hardware-counter scale)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        torch.cuda.set_device(0)
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (particles are independent, "
               f"a multi-GPU run would shard them with no per-iteration exchange)", file=sys.stderr)

@@ -210,6 +210,41 @@ size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg);
 int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
                 float *d_best_q, float *d_best_pose, spasm_result *out, void *stream);
 
+/* --- serving (continuous batching) --------------------------------------------------------
+ * A server owns one device arena of hbm_budget bytes and max_slots solve slots on its own
+ * stream.  Requests are queued by spasm_server_submit.  Each spasm_server_step:
+ *   1. admits queued requests in arrival order while a slot is free and the request's
+ *      footprint (spasm_server_footprint) fits in the arena, and runs their stage 1, lift
+ *      and seeding;
+ *   2. advances every admitted solve by up to iters_per_step stage-2 iterations in ONE
+ *      launch per (waypoint slots, sphere chunk) class -- solves of different block
+ *      counts, waypoint counts and clutter share a launch, each particle is a workgroup,
+ *      and the state stays on the device between steps;
+ *   3. finishes solves that reached K (final evaluation, best particle written to the
+ *      d_best_q [2B][W][7] / d_best_pose [B][4] buffers given at submit time) and queues
+ *      their completion records;
+ * then synchronises its stream.  A request's result is the same whatever else is in the
+ * batch (every particle runs the same code on its own state).  Not thread-safe: one
+ * thread drives a server; the problem and output buffers of a request must stay valid
+ * until its completion is polled.  spasm_server_submit returns SPASM_EBUSY when the
+ * request can never fit (footprint > budget). */
+typedef struct spasm_server_s *spasm_server;
+
+typedef struct {
+    uint64_t req_id;
+    int32_t status;      /* SPASM_OK, or the error that ended the request */
+    int32_t steps;       /* server steps between admission and completion */
+    spasm_result result; /* per-request stage times are not measured (0) */
+} spasm_completion;
+
+size_t spasm_server_footprint(spasm_problem prob, const spasm_solve_config *cfg);
+int spasm_server_create(size_t hbm_budget, int32_t max_slots, int32_t iters_per_step, spasm_server *out);
+int spasm_server_submit(spasm_server srv, spasm_problem prob, const spasm_solve_config *cfg, uint64_t req_id,
+                        float *d_best_q, float *d_best_pose);
+int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n_pending);
+int spasm_server_poll(spasm_server srv, spasm_completion *out, int32_t max, int32_t *n_out);
+void spasm_server_destroy(spasm_server srv);
+
 const char *spasm_last_error(void);
 
 #ifdef __cplusplus

@@ -12,11 +12,24 @@
 #include "spasm_internal.h"
 
 using namespace spasm;
+using spasm::fail;
 
 namespace {
-
 thread_local std::string g_err;
+std::mutex g_attr_mu;
+bool g_attr_done[64];
 
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool valid_W(int W) { return W == 4 || W == 8 || W == 16 || W == 32 || W == 64; }
+}  // namespace
+
+namespace spasm {
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -28,23 +41,7 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define SPASM_HIP(expr)                                                                  \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) return fail(SPASM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-bool finite_all(const double *p, size_t n)
-{
-    for (size_t i = 0; i < n; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
-}
-
-bool valid_W(int W) { return W == 4 || W == 8 || W == 16 || W == 32 || W == 64; }
-
-std::mutex g_attr_mu;
-bool g_attr_done[64];
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int ensure_attrs()
 {
@@ -58,20 +55,15 @@ int ensure_attrs()
     return SPASM_OK;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-}  // namespace
-
-struct spasm_problem_s {
-    KProb kp;
-    void *dmem = nullptr;
-    int device = 0;
-    int k_total1 = 0;
-    int retries = 0;
-    double lin_frac2 = 0.0;
-    float sat_eps = 1e-3f;
-    int ik_iters = 0;
-};
+int check_traj_shape(int B, int P, int W)
+{
+    if (P < 1) return fail(SPASM_EINVAL, "P=%d must be >= 1", P);
+    if (!valid_W(W)) return fail(SPASM_EUNSUPPORTED, "W=%d must be 4, 8, 16, 32 or 64", W);
+    if (2 * B * W > MAX_THREADS)
+        return fail(SPASM_EUNSUPPORTED, "2*B*W=%d exceeds %d waypoint slots per particle", 2 * B * W, MAX_THREADS);
+    return SPASM_OK;
+}
+}  // namespace spasm
 
 extern "C" const char *spasm_last_error(void) { return g_err.c_str(); }
 
@@ -293,14 +285,7 @@ extern "C" void spasm_problem_destroy(spasm_problem prob)
 
 extern "C" int spasm_problem_blocks(spasm_problem prob) { return prob ? prob->kp.B : 0; }
 
-static int check_traj_shape(spasm_problem prob, int P, int W)
-{
-    if (P < 1) return fail(SPASM_EINVAL, "P=%d must be >= 1", P);
-    if (!valid_W(W)) return fail(SPASM_EUNSUPPORTED, "W=%d must be 4, 8, 16, 32 or 64", W);
-    if (2 * prob->kp.B * W > MAX_THREADS)
-        return fail(SPASM_EUNSUPPORTED, "2*B*W=%d exceeds %d waypoint slots per particle", 2 * prob->kp.B * W, MAX_THREADS);
-    return SPASM_OK;
-}
+static int check_traj_shape(spasm_problem prob, int P, int W) { return spasm::check_traj_shape(prob->kp.B, P, W); }
 
 extern "C" int spasm_sample(spasm_problem prob, int32_t N, uint64_t seed, int32_t round, float *d_x, void *stream)
 {
@@ -457,11 +442,23 @@ extern "C" int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const f
 // whole method
 // ---------------------------------------------------------------------------------------
 namespace {
-struct SolveLayout {
-    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, pose, qg, qp, q, c2, v2, ord2, nsat2, info, finfo, total;
-};
+__global__ void k_zero_words(uint32_t *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+}  // namespace
 
-SolveLayout layout(const KProb &K, const spasm_solve_config &c)
+namespace spasm {
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c)
 {
     SolveLayout L{};
     size_t off = 0;
@@ -508,20 +505,58 @@ int check_cfg(spasm_problem prob, const spasm_solve_config *cfg)
         return fail(SPASM_EINVAL, "fixed-goal problems take N1 = 0");
     }
     if (cfg->K < 0) return fail(SPASM_EINVAL, "K must be >= 0");
-    return check_traj_shape(prob, cfg->M, cfg->W);
+    return check_traj_shape(prob->kp.B, cfg->M, cfg->W);
 }
 
-__global__ void k_zero_ints(int *p, int n)
+int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L, hipStream_t st,
+                   hipEvent_t after_stage1)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+    const KProb &K = prob->kp;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    const int M = cfg.M, W = cfg.W;
+    if (cfg.N1 > 0) {
+        SPASM_HIP(launch_zero(I(L.done), 4, st));
+        SPASM_HIP(launch_zero(I(L.info), 32, st));
+        const int R = prob->retries;
+        for (int r = 0; r <= R; ++r) {
+            const int *skip = I(L.done);
+            SPASM_HIP(launch_sample(K, cfg.N1, cfg.seed, r, F(L.x1), skip, st));
+            SPASM_HIP(launch_place(K, cfg.N1, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1),
+                                   nullptr, skip, st));
+            SPASM_HIP(launch_sort_keys(0, cfg.N1, F(L.c1), nullptr, 0.f, M, I(L.idx), nullptr, skip, st));
+            SPASM_HIP(launch_place(K, M, F(L.x1), I(L.idx), F(L.xs), 1, prob->k_total1 + 1, SPASM_PHASE_QUAD,
+                                   F(L.cs), F(L.vs), nullptr, skip, st));
+            SPASM_HIP(launch_sort_keys(1, M, F(L.cs), F(L.vs), prob->sat_eps, M, I(L.ord1), I(L.nsat1), skip, st));
+            SPASM_HIP(launch_commit_stage1(K, M, r, r == R, F(L.xs), I(L.ord1), I(L.nsat1), F(L.pose), I(L.done),
+                                           I(L.info), st));
+        }
+    } else {
+        SPASM_HIP(launch_fixed_poses(K, M, F(L.pose), I(L.info), st));
+    }
+    if (after_stage1) SPASM_HIP(hipEventRecord(after_stage1, st));
+    SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg.seed, prob->ik_iters, F(L.qg), F(L.qp), st));
+    SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), cfg.seed, F(L.q), st));
+    return SPASM_OK;
 }
-}  // namespace
+
+int enqueue_finish(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L, float *best_q,
+                   float *best_pose, hipStream_t st)
+{
+    const KProb &K = prob->kp;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    SPASM_HIP(launch_sort_keys(1, cfg.M, F(L.c2), F(L.v2), prob->sat_eps, cfg.M, I(L.ord2), I(L.nsat2), nullptr, st));
+    SPASM_HIP(launch_finalize(K, cfg.M, cfg.W, F(L.q), F(L.pose), F(L.c2), F(L.v2), I(L.ord2), I(L.nsat2), best_q,
+                              best_pose, I(L.info), F(L.finfo), st));
+    return SPASM_OK;
+}
+}  // namespace spasm
 
 extern "C" size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg)
 {
     if (check_cfg(prob, cfg)) return 0;
-    return layout(prob->kp, *cfg).total;
+    return solve_layout(prob->kp, *cfg).total;
 }
 
 extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
@@ -532,7 +567,7 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     if (!d_work || !d_best_q || !d_best_pose || !out) return fail(SPASM_EINVAL, "NULL buffer");
     if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace must be 256-byte aligned");
     const KProb &K = prob->kp;
-    const SolveLayout L = layout(K, *cfg);
+    const SolveLayout L = solve_layout(K, *cfg);
     if (work_bytes < L.total) return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, L.total);
     rc = ensure_attrs();
     if (rc) return rc;
@@ -540,7 +575,6 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     char *w = (char *)d_work;
     auto F = [&](size_t o) { return (float *)(w + o); };
     auto I = [&](size_t o) { return (int32_t *)(w + o); };
-    const int M = cfg->M, W = cfg->W;
 
     hipEvent_t ev[5];
     for (int i = 0; i < 5; ++i) SPASM_HIP(hipEventCreate(&ev[i]));
@@ -553,33 +587,11 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     } guard{ev};
 
     SPASM_HIP(hipEventRecord(ev[0], st));
-    if (cfg->N1 > 0) {
-        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, I(L.done), 1);
-        SPASM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, I(L.info), 8);
-        SPASM_HIP(hipGetLastError());
-        const int R = prob->retries;
-        for (int r = 0; r <= R; ++r) {
-            const int *skip = I(L.done);
-            SPASM_HIP(launch_sample(K, cfg->N1, cfg->seed, r, F(L.x1), skip, st));
-            SPASM_HIP(launch_place(K, cfg->N1, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1),
-                                   nullptr, skip, st));
-            SPASM_HIP(launch_sort_keys(0, cfg->N1, F(L.c1), nullptr, 0.f, M, I(L.idx), nullptr, skip, st));
-            SPASM_HIP(launch_place(K, M, F(L.x1), I(L.idx), F(L.xs), 1, prob->k_total1 + 1, SPASM_PHASE_QUAD,
-                                   F(L.cs), F(L.vs), nullptr, skip, st));
-            SPASM_HIP(launch_sort_keys(1, M, F(L.cs), F(L.vs), prob->sat_eps, M, I(L.ord1), I(L.nsat1), skip, st));
-            SPASM_HIP(launch_commit_stage1(K, M, r, r == R, F(L.xs), I(L.ord1), I(L.nsat1), F(L.pose), I(L.done),
-                                           I(L.info), st));
-        }
-    } else {
-        SPASM_HIP(launch_fixed_poses(K, M, F(L.pose), I(L.info), st));
-    }
-    SPASM_HIP(hipEventRecord(ev[1], st));
-    SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg->seed, prob->ik_iters, F(L.qg), F(L.qp), st));
-    SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), cfg->seed, F(L.q), st));
+    rc = enqueue_prefix(prob, *cfg, w, L, st, ev[1]);
+    if (rc) return rc;
     TrajArgs a{};
-    a.P = M;
-    a.W = W;
+    a.P = cfg->M;
+    a.W = cfg->W;
     a.q_in = F(L.q);
     a.pose_in = F(L.pose);
     a.q_out = F(L.q);
@@ -592,9 +604,8 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     SPASM_HIP(hipEventRecord(ev[3], st));
     SPASM_HIP(launch_traj(K, 2, a, st));
     SPASM_HIP(hipEventRecord(ev[4], st));
-    SPASM_HIP(launch_sort_keys(1, M, F(L.c2), F(L.v2), prob->sat_eps, M, I(L.ord2), I(L.nsat2), nullptr, st));
-    SPASM_HIP(launch_finalize(K, M, W, F(L.q), F(L.pose), F(L.c2), F(L.v2), I(L.ord2), I(L.nsat2), d_best_q,
-                              d_best_pose, I(L.info), F(L.finfo), st));
+    rc = enqueue_finish(prob, *cfg, w, L, d_best_q, d_best_pose, st);
+    if (rc) return rc;
     SPASM_HIP(hipEventRecord(ev[2], st));
     int32_t info[8];
     float finfo[4];

@@ -45,6 +45,12 @@ __device__ __forceinline__ float wave_sum(float v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
 __device__ __forceinline__ float wave_max(float v)
 {
 #pragma unroll
@@ -190,6 +196,85 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
                         wt[0] += cy[i] * fz - cz[i] * fy;
                         wt[1] += cz[i] * fx - cx[i] * fz;
                         wt[2] += cx[i] * fy - cy[i] * fx;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Broad phase for collide_boxes: the wave's active lanes' spheres are bounded by one
+// axis-aligned box (exact min/max over lanes, 1e-4 m margin against rounding); each lane
+// tests one obstacle against it, and only the obstacles that overlap it go through the
+// sphere-box tests.  A skipped obstacle cannot touch any sphere of the wave, so the
+// result is identical to testing every obstacle.
+template <bool GRAD, int CH>
+__device__ __forceinline__ void collide_boxes_culled(const KProb &P, int phase, float wgt, const float (&cx)[CH],
+                                                     const float (&cy)[CH], const float (&cz)[CH],
+                                                     const float (&r)[CH], bool act, float &cost, float &viol,
+                                                     float (&wf)[3], float (&wt)[3])
+{
+    float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            lo0 = fminf(lo0, cx[i] - r[i]);
+            lo1 = fminf(lo1, cy[i] - r[i]);
+            lo2 = fminf(lo2, cz[i] - r[i]);
+            hi0 = fmaxf(hi0, cx[i] + r[i]);
+            hi1 = fmaxf(hi1, cy[i] + r[i]);
+            hi2 = fmaxf(hi2, cz[i] + r[i]);
+        }
+    }
+    lo0 = wave_min(lo0) - 1e-4f;
+    lo1 = wave_min(lo1) - 1e-4f;
+    lo2 = wave_min(lo2) - 1e-4f;
+    hi0 = wave_max(hi0) + 1e-4f;
+    hi1 = wave_max(hi1) + 1e-4f;
+    hi2 = wave_max(hi2) + 1e-4f;
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < P.O; base += 64) {
+        const int ol = base + lane;
+        bool ov = false;
+        if (ol < P.O) {
+            const float4 bc = ldc(P.box, 2 * ol), be = ldc(P.box, 2 * ol + 1);
+            ov = bc.x - be.x <= hi0 && bc.x + be.x >= lo0 && bc.y - be.y <= hi1 && bc.y + be.y >= lo1 &&
+                 bc.z - be.z <= hi2 && bc.z + be.z >= lo2;
+        }
+        unsigned long long m = __ballot(ov);
+        while (m) {
+            const int o = base + __builtin_ctzll(m);
+            m &= m - 1;
+            const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
+            bool hit = false;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const float ux = fabsf(cx[i] - bc.x) - be.x;
+                const float uy = fabsf(cy[i] - bc.y) - be.y;
+                const float uz = fabsf(cz[i] - bc.z) - be.z;
+                hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
+            }
+            if (hit && act) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
+                    const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
+                    float gx, gy, gz;
+                    const float sdf = box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
+                    const float delta = r[i] - sdf;
+                    if (delta > 0.f) {
+                        cost += wgt * phi(phase, delta);
+                        viol = fmaxf(viol, delta);
+                        if (GRAD) {
+                            const float sc = -wgt * dphi(phase, delta);
+                            const float fx = sc * gx, fy = sc * gy, fz = sc * gz;
+                            wf[0] += fx;
+                            wf[1] += fy;
+                            wf[2] += fz;
+                            wt[0] += cy[i] * fz - cz[i] * fy;
+                            wt[1] += cz[i] * fx - cx[i] * fz;
+                            wt[2] += cx[i] * fy - cy[i] * fx;
+                        }
                     }
                 }
             }
@@ -801,9 +886,10 @@ __device__ __forceinline__ float adam_update(float x, float &m, float &v, float 
     return x - (lr / bc1) * m / (sqrtf(v) / bc2s + eps);
 }
 
-// MODE 0: cost, 1: cost + gradient (optionally scaled per particle), 2: optimise.
+// One particle per workgroup.  MODE 0: cost, 1: cost + gradient (optionally scaled per
+// particle), 2: optimise.  s_mv: dynamic LDS, [2][NJ][blockDim.x] Adam moments (MODE 2).
 template <int MODE, int CH>
-__global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
+__device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a, int p, float *s_mv)
 {
     __shared__ float s_pose[2 * MAX_B * 8];
     __shared__ float s_pacc[16 * MAX_B * 4];
@@ -812,9 +898,8 @@ __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
     __shared__ float s_tie[2][2 * MAX_B][8];
     __shared__ float s_red[16][2];
     __shared__ float s_popt[2][MAX_B * 4];
-    extern __shared__ float s_mv[];  // MODE 2: [2][NJ][blockDim.x] Adam moments
 
-    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const int B = P.B, W = a.W, NS = 2 * B, BW = B * W;
     Slot sl;
     sl.active = tid < 2 * BW;
@@ -993,6 +1078,37 @@ __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
             a.gpose[((size_t)p * B + bb) * 4 + c] = gsum * scale;
         }
     }
+}
+
+template <int MODE, int CH>
+__global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
+{
+    extern __shared__ float s_mv[];
+    traj_particle<MODE, CH>(P, a, blockIdx.x, s_mv);
+}
+
+// Serving: one launch advances every active solve of one (thread count, sphere chunk)
+// class; workgroup w belongs to the last solve whose `first` is <= w.  Descriptors are
+// read through the constant address space so that their fields stay in scalar registers.
+typedef __attribute__((address_space(4))) const char cchar;
+
+template <int CH>
+__global__ __launch_bounds__(1024) void k_serve(const ServeSolve *solves, int nsolve)
+{
+    extern __shared__ float s_mv[];
+    cchar *base = (cchar *)solves;
+    const int wg = blockIdx.x;
+    int lo = 0, hi = nsolve - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int first = *(const int *)(base + (size_t)mid * sizeof(ServeSolve) + offsetof(ServeSolve, first));
+        if (first <= wg)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ServeSolve &d = *(const ServeSolve *)(base + (size_t)lo * sizeof(ServeSolve));
+    traj_particle<2, CH>(d.P, d.a, wg - d.first, s_mv);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1395,12 +1511,27 @@ hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t 
     }
 }
 
+hipError_t launch_serve(int chunk, int threads, int nwg, const ServeSolve *d_solves, int nsolve, hipStream_t st)
+{
+    const size_t shm = (size_t)2 * NJ * threads * sizeof(float);
+    switch (chunk) {
+    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
+    case 6: hipLaunchKernelGGL(k_serve<6>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
+    case 7: hipLaunchKernelGGL(k_serve<7>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
+    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
     if (e != hipSuccess) return e;
 #define SPASM_TRAJ_ATTR(CH)                                                                                      \
     e = hipFuncSetAttribute((const void *)k_traj<2, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
+    if (e != hipSuccess) return e;                                                                           \
+    e = hipFuncSetAttribute((const void *)k_serve<CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
     if (e != hipSuccess) return e;
     SPASM_TRAJ_ATTR(4)
     SPASM_TRAJ_ATTR(6)

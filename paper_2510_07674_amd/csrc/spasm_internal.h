@@ -2,7 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "spasm.h"
 
 namespace spasm {
 
@@ -63,6 +66,17 @@ struct TrajArgs {
 };
 // mode 0: cost only, 1: cost + gradient (scaled by gout if given), 2: optimise
 hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st);
+
+// One active solve in a serving launch: its problem, its stage-2 state and the steps of
+// this launch; workgroups [first, first + a.P) of the launch are its particles.
+struct ServeSolve {
+    KProb P;
+    TrajArgs a;
+    int first;
+    int pad[3];
+};
+// nwg = total particles of the class; d_solves sorted by `first`, device memory
+hipError_t launch_serve(int chunk, int threads, int nwg, const ServeSolve *d_solves, int nsolve, hipStream_t st);
 int traj_threads(int B, int W);
 // raise the dynamic-LDS ceilings of the sort and optimise kernels
 hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes);
@@ -88,4 +102,42 @@ hipError_t launch_finalize(const KProb &P, int M, int W, const float *q, const f
                            const int32_t *nsat, float *best_q, float *best_pose, int32_t *info,
                            float *finfo, hipStream_t st);
 
+// ---- shared host helpers (api.hip) ----
+int fail(int code, const char *fmt, ...);  // records the thread-local message, returns code
+size_t align256(size_t x);
+int ensure_attrs();
+int check_traj_shape(int B, int P, int W);
+
+// Workspace layout of one solve (offsets in bytes from the workspace base).
+struct SolveLayout {
+    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, pose, qg, qp, q, c2, v2, ord2, nsat2, info, finfo, total;
+};
+SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c);
+int check_cfg(spasm_problem prob, const spasm_solve_config *cfg);
+// Stage 1 (or fixed goals), lift and seeding into the workspace, on `st`.
+// after_stage1 (nullable) is recorded between stage 1 and the lift.
+int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L, hipStream_t st,
+                   hipEvent_t after_stage1 = nullptr);
+// Final ordering, best particle copied to best_q / best_pose, summary in info/finfo.
+int enqueue_finish(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L,
+                   float *best_q, float *best_pose, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
 }  // namespace spasm
+
+struct spasm_problem_s {
+    spasm::KProb kp;
+    void *dmem = nullptr;
+    int device = 0;
+    int k_total1 = 0;
+    int retries = 0;
+    double lin_frac2 = 0.0;
+    float sat_eps = 1e-3f;
+    int ik_iters = 0;
+};
+
+#define SPASM_HIP(expr)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return spasm::fail(SPASM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)

@@ -49,6 +49,10 @@ class ResultDesc(ctypes.Structure):
                 ("opt_ms", ctypes.c_float)]
 
 
+class CompletionDesc(ctypes.Structure):
+    _fields_ = [("req_id", c_u64), ("status", c_i32), ("steps", c_i32), ("result", ResultDesc)]
+
+
 SYMBOLS = {
     "spasm_problem_create": ([ctypes.POINTER(ChainDesc), c_i32, c_vp, c_vp, c_vp, c_i32, c_vp,
                               ctypes.POINTER(SkeletonDesc), ctypes.POINTER(ParamsDesc), ctypes.POINTER(c_vp)], c_i32),
@@ -66,6 +70,12 @@ SYMBOLS = {
     "spasm_solve_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
     "spasm_solve": ([c_vp, ctypes.POINTER(SolveConfigDesc), c_vp, ctypes.c_size_t, c_vp, c_vp,
                      ctypes.POINTER(ResultDesc), c_vp], c_i32),
+    "spasm_server_footprint": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
+    "spasm_server_create": ([ctypes.c_size_t, c_i32, c_i32, ctypes.POINTER(c_vp)], c_i32),
+    "spasm_server_submit": ([c_vp, c_vp, ctypes.POINTER(SolveConfigDesc), c_u64, c_vp, c_vp], c_i32),
+    "spasm_server_step": ([c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)], c_i32),
+    "spasm_server_poll": ([c_vp, ctypes.POINTER(CompletionDesc), c_i32, ctypes.POINTER(c_i32)], c_i32),
+    "spasm_server_destroy": ([c_vp], None),
     "spasm_last_error": ([], ctypes.c_char_p),
 }
 
@@ -282,6 +292,60 @@ class Problem:
                                   _dev(best_pose, (self.B, 4), name="best_pose"), ctypes.byref(res), _stream()))
         out = {f: getattr(res, f) for f, _ in ResultDesc._fields_}
         return out, best_q, best_pose
+
+
+class Server:
+    """Continuous-batching server (spasm_server_*): submit requests, call step() to admit,
+    advance and retire, poll() completions.  Keeps each request's problem and output
+    tensors alive until its completion has been polled."""
+
+    def __init__(self, hbm_budget, max_slots=64, iters_per_step=25):
+        h = c_vp()
+        _check(load().spasm_server_create(int(hbm_budget), int(max_slots), int(iters_per_step), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+
+    @staticmethod
+    def footprint(problem, cfg):
+        c = problem.config_desc(cfg)
+        return int(load().spasm_server_footprint(problem.handle, ctypes.byref(c)))
+
+    def submit(self, problem, cfg, req_id):
+        c = problem.config_desc(cfg)
+        best_q = _empty(2 * problem.B, cfg.W, 7)
+        best_pose = _empty(problem.B, 4)
+        _check(load().spasm_server_submit(self.handle, problem.handle, ctypes.byref(c), int(req_id),
+                                          _dev(best_q), _dev(best_pose)))
+        self._live[int(req_id)] = (problem, best_q, best_pose)
+
+    def step(self):
+        na, npend = c_i32(), c_i32()
+        _check(load().spasm_server_step(self.handle, ctypes.byref(na), ctypes.byref(npend)))
+        return na.value, npend.value
+
+    def poll(self, max_n=256):
+        arr = (CompletionDesc * max_n)()
+        n = c_i32()
+        _check(load().spasm_server_poll(self.handle, arr, max_n, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            res = {f: getattr(c.result, f) for f, _ in ResultDesc._fields_}
+            _, bq, bp = self._live.pop(int(c.req_id))
+            out.append({"req_id": int(c.req_id), "status": c.status, "steps": c.steps, "result": res,
+                        "best_q": bq, "best_pose": bp})
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().spasm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def select_topm(key, M):
