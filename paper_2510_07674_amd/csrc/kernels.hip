@@ -39,23 +39,60 @@ __device__ __forceinline__ float zstar(const KProb &P, int b)
     return P.mode == 0 ? ((float)b + 0.5f) * P.h : ldc(P.goal, 2 * b).z;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// Cross-lane reductions without LDS: DPP within each 16-lane row (quad_perm xor 1 and
+// xor 2, row_mirror, row_half_mirror) and the gfx950 row swaps across rows (xor 32, then
+// xor 16).  Every step combines a lane with its partner in the same operand order on
+// both sides, so all 64 lanes end with bit-identical results, also for sums.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
-__device__ __forceinline__ float wave_min(float v)
+struct OpSum {
+    __device__ __forceinline__ float operator()(float a, float b) const { return a + b; }
+};
+struct OpMin {
+    __device__ __forceinline__ float operator()(float a, float b) const { return fminf(a, b); }
+};
+struct OpMax {
+    __device__ __forceinline__ float operator()(float a, float b) const { return fmaxf(a, b); }
+};
+// within groups of 8 lanes (xor 1, xor 2, then quad q with quad q ^ 1 through the half-row
+// mirror)
+template <class Op>
+__device__ __forceinline__ float group8_reduce(float v, Op op)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
+    v = op(v, dpp<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = op(v, dpp<0x4E>(v));   // quad_perm [2,3,0,1]
+    return op(v, dpp<0x141>(v));  // row_half_mirror
 }
-__device__ __forceinline__ float wave_max(float v)
+template <class Op>
+__device__ __forceinline__ float wave_reduce(float v, Op op)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
+    v = group8_reduce(v, op);
+    v = op(v, dpp<0x140>(v));  // row_mirror: half-row h with 1 - h
+    const int b = __float_as_int(v);
+    const auto s32 = __builtin_amdgcn_permlane32_swap(b, b, false, false);
+    v = op(__int_as_float(s32[0]), __int_as_float(s32[1]));
+    const int c = __float_as_int(v);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(c, c, false, false);
+    return op(__int_as_float(s16[0]), __int_as_float(s16[1]));
+}
+// whole-wave shifts by one lane (lane i reads i + 1, resp. i - 1); the end lane keeps its value
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum(float v) { return wave_reduce(v, OpSum()); }
+__device__ __forceinline__ float wave_min(float v) { return wave_reduce(v, OpMin()); }
+__device__ __forceinline__ float wave_max(float v) { return wave_reduce(v, OpMax()); }
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 // Alg. 1 schedule: eta_k = eta (1 - k / k_lin) on the linear cost for k <= k_lin, then the
@@ -156,63 +193,41 @@ __device__ __forceinline__ float box_sdf(float dx, float dy, float dz, float ux,
 }
 
 // ------------------------------------------------------------------------------------
-// Sphere sets against obstacles (axis-aligned boxes, scalar-loaded) and blocks (yawed
-// cubes from the LDS pose table).  CH spheres are tested per box so the box parameters
-// are fetched once per chunk; the exact distance and gradient run only in the (rare)
-// branch where some lane's sphere overlaps the box's slab test.
+// Sphere sets against obstacles (axis-aligned boxes) and blocks (yawed cubes from the
+// LDS pose table), CH spheres per lane at a time.
+//
+// Obstacles, broad phase: the chunk's spheres over the wave's active lanes are bounded by
+// one axis-aligned box (exact min/max, 1e-4 m margin against rounding, held in SGPRs);
+// each lane tests one obstacle against it and a ballot keeps the obstacles that overlap.
+// A skipped obstacle cannot touch any sphere of the wave.
+// Narrow phase per kept obstacle (parameters in SGPRs): a slab test per sphere, which is
+// necessary for penetration (sdf >= max(|d| - e)), gives one ballot mask per sphere; the
+// exact distance and gradient run only for the spheres that some lane's slab test hits.
 // ------------------------------------------------------------------------------------
+template <bool GRAD>
+__device__ __forceinline__ void contact(int phase, float wgt, float cx, float cy, float cz, float sdf, float r,
+                                        float gx, float gy, float gz, float &cost, float &viol, float (&wf)[3],
+                                        float (&wt)[3])
+{
+    const float delta = r - sdf;
+    cost += wgt * phi(phase, delta);
+    viol = fmaxf(viol, delta);
+    if (GRAD) {
+        const float sc = -wgt * dphi(phase, delta);
+        const float fx = sc * gx, fy = sc * gy, fz = sc * gz;
+        wf[0] += fx;
+        wf[1] += fy;
+        wf[2] += fz;
+        wt[0] += cy * fz - cz * fy;
+        wt[1] += cz * fx - cx * fz;
+        wt[2] += cx * fy - cy * fx;
+    }
+}
+
 template <bool GRAD, int CH>
 __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
                                               const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
                                               bool act, float &cost, float &viol, float (&wf)[3], float (&wt)[3])
-{
-    for (int o = 0; o < P.O; ++o) {
-        const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
-        bool hit = false;
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const float ux = fabsf(cx[i] - bc.x) - be.x;
-            const float uy = fabsf(cy[i] - bc.y) - be.y;
-            const float uz = fabsf(cz[i] - bc.z) - be.z;
-            hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
-        }
-        if (hit && act) {
-#pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
-                const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
-                float gx, gy, gz;
-                const float sdf = box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
-                const float delta = r[i] - sdf;
-                if (delta > 0.f) {
-                    cost += wgt * phi(phase, delta);
-                    viol = fmaxf(viol, delta);
-                    if (GRAD) {
-                        const float sc = -wgt * dphi(phase, delta);
-                        const float fx = sc * gx, fy = sc * gy, fz = sc * gz;
-                        wf[0] += fx;
-                        wf[1] += fy;
-                        wf[2] += fz;
-                        wt[0] += cy[i] * fz - cz[i] * fy;
-                        wt[1] += cz[i] * fx - cx[i] * fz;
-                        wt[2] += cx[i] * fy - cy[i] * fx;
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Broad phase for collide_boxes: the wave's active lanes' spheres are bounded by one
-// axis-aligned box (exact min/max over lanes, 1e-4 m margin against rounding); each lane
-// tests one obstacle against it, and only the obstacles that overlap it go through the
-// sphere-box tests.  A skipped obstacle cannot touch any sphere of the wave, so the
-// result is identical to testing every obstacle.
-template <bool GRAD, int CH>
-__device__ __forceinline__ void collide_boxes_culled(const KProb &P, int phase, float wgt, const float (&cx)[CH],
-                                                     const float (&cy)[CH], const float (&cz)[CH],
-                                                     const float (&r)[CH], bool act, float &cost, float &viol,
-                                                     float (&wf)[3], float (&wt)[3])
 {
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     if (act) {
@@ -225,13 +240,19 @@ __device__ __forceinline__ void collide_boxes_culled(const KProb &P, int phase, 
             hi1 = fmaxf(hi1, cy[i] + r[i]);
             hi2 = fmaxf(hi2, cz[i] + r[i]);
         }
+        lo0 -= 1e-4f;
+        lo1 -= 1e-4f;
+        lo2 -= 1e-4f;
+        hi0 += 1e-4f;
+        hi1 += 1e-4f;
+        hi2 += 1e-4f;
     }
-    lo0 = wave_min(lo0) - 1e-4f;
-    lo1 = wave_min(lo1) - 1e-4f;
-    lo2 = wave_min(lo2) - 1e-4f;
-    hi0 = wave_max(hi0) + 1e-4f;
-    hi1 = wave_max(hi1) + 1e-4f;
-    hi2 = wave_max(hi2) + 1e-4f;
+    lo0 = uniform(wave_min(lo0));
+    lo1 = uniform(wave_min(lo1));
+    lo2 = uniform(wave_min(lo2));
+    hi0 = uniform(wave_max(hi0));
+    hi1 = uniform(wave_max(hi1));
+    hi2 = uniform(wave_max(hi2));
     const int lane = threadIdx.x & 63;
     for (int base = 0; base < P.O; base += 64) {
         const int ol = base + lane;
@@ -246,37 +267,25 @@ __device__ __forceinline__ void collide_boxes_culled(const KProb &P, int phase, 
             const int o = base + __builtin_ctzll(m);
             m &= m - 1;
             const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
-            bool hit = false;
+            unsigned long long hm[CH], any = 0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const float ux = fabsf(cx[i] - bc.x) - be.x;
                 const float uy = fabsf(cy[i] - bc.y) - be.y;
                 const float uz = fabsf(cz[i] - bc.z) - be.z;
-                hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
+                hm[i] = __ballot(act && fmaxf(fmaxf(ux, uy), uz) < r[i]);
+                any |= hm[i];
             }
-            if (hit && act) {
+            if (!any) continue;
 #pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
-                    const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
-                    float gx, gy, gz;
-                    const float sdf = box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
-                    const float delta = r[i] - sdf;
-                    if (delta > 0.f) {
-                        cost += wgt * phi(phase, delta);
-                        viol = fmaxf(viol, delta);
-                        if (GRAD) {
-                            const float sc = -wgt * dphi(phase, delta);
-                            const float fx = sc * gx, fy = sc * gy, fz = sc * gz;
-                            wf[0] += fx;
-                            wf[1] += fy;
-                            wf[2] += fz;
-                            wt[0] += cy[i] * fz - cz[i] * fy;
-                            wt[1] += cz[i] * fx - cx[i] * fz;
-                            wt[2] += cx[i] * fy - cy[i] * fx;
-                        }
-                    }
-                }
+            for (int i = 0; i < CH; ++i) {
+                if (!hm[i]) continue;
+                const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
+                const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
+                float gx, gy, gz;
+                const float sdf = box_sdf(dx, dy, dz, ux, uy, uz, gx, gy, gz);
+                if (act && r[i] - sdf > 0.f)
+                    contact<GRAD>(phase, wgt, cx[i], cy[i], cz[i], sdf, r[i], gx, gy, gz, cost, viol, wf, wt);
             }
         }
     }
@@ -299,44 +308,34 @@ __device__ __forceinline__ void collide_blocks(const KProb &P, int phase, float 
         const bool vis = act && (bb != b || own_visible);
         const float *pp = s_pose + ((movable ? 0 : MAX_B) + bb) * 8;
         const float tx = pp[0], ty = pp[1], tz = pp[2], cs = pp[4], sn = pp[5];
-        bool hit = false;
+        unsigned long long hm[CH], any = 0;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
             const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
             const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
-            hit |= fmaxf(fmaxf(ux, uy), uz) < r[i];
+            hm[i] = __ballot(vis && fmaxf(fmaxf(ux, uy), uz) < r[i]);
+            any |= hm[i];
         }
+        if (!any) continue;
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-        if (hit && vis) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
-                const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
-                const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
-                float gx, gy, gz;
-                const float sdf = box_sdf(lx, ly, dz, ux, uy, uz, gx, gy, gz);
-                const float delta = r[i] - sdf;
-                if (delta > 0.f) {
-                    cost += wgt * phi(phase, delta);
-                    viol = fmaxf(viol, delta);
-                    if (GRAD) {
-                        const float sc = -wgt * dphi(phase, delta);
-                        const float wx = cs * gx - sn * gy, wy = sn * gx + cs * gy;  // world gradient
-                        const float fx = sc * wx, fy = sc * wy, fz = sc * gz;
-                        wf[0] += fx;
-                        wf[1] += fy;
-                        wf[2] += fz;
-                        wt[0] += cy[i] * fz - cz[i] * fy;
-                        wt[1] += cz[i] * fx - cx[i] * fz;
-                        wt[2] += cx[i] * fy - cy[i] * fx;
-                        if (movable) {
-                            g0 -= fx;
-                            g1 -= fy;
-                            g2 -= fz;
-                            g3 += sc * (gx * ly - gy * lx);
-                        }
-                    }
+        for (int i = 0; i < CH; ++i) {
+            if (!hm[i]) continue;
+            const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
+            const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
+            const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
+            float gx, gy, gz;
+            const float sdf = box_sdf(lx, ly, dz, ux, uy, uz, gx, gy, gz);
+            if (vis && r[i] - sdf > 0.f) {
+                const float wx = cs * gx - sn * gy, wy = sn * gx + cs * gy;  // world gradient
+                contact<GRAD>(phase, wgt, cx[i], cy[i], cz[i], sdf, r[i], wx, wy, gz, cost, viol, wf, wt);
+                if (GRAD && movable) {
+                    const float sc = -wgt * dphi(phase, r[i] - sdf);
+                    g0 -= sc * wx;
+                    g1 -= sc * wy;
+                    g2 -= sc * gz;
+                    g3 += sc * (gx * ly - gy * lx);
                 }
             }
         }
@@ -833,8 +832,8 @@ __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const S
     const float w_s = P.w[W_SMOOTH];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const float qn = __shfl_down(q[j], 1, 64);
-        const float qp = __shfl_up(q[j], 1, 64);
+        const float qn = lane_next(q[j]);
+        const float qp = lane_prev(q[j]);
         if (sl.active && sl.w < W - 1) {
             const float d = qn - q[j];
             cost += w_s * d * d;
@@ -849,12 +848,7 @@ __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const S
         if (i < P.B) place_lane<GRAD>(P, phase, i, k, s_pose, cost, viol, gp);
         if (GRAD) {
 #pragma unroll
-            for (int m = 1; m < 8; m <<= 1) {
-                gp[0] += __shfl_xor(gp[0], m, 64);
-                gp[1] += __shfl_xor(gp[1], m, 64);
-                gp[2] += __shfl_xor(gp[2], m, 64);
-                gp[3] += __shfl_xor(gp[3], m, 64);
-            }
+            for (int c = 0; c < 4; ++c) gp[c] = group8_reduce(gp[c], OpSum());
             if (k == 0 && i < P.B) {
                 s_placeg[i * 4 + 0] = gp[0];
                 s_placeg[i * 4 + 1] = gp[1];
