@@ -158,14 +158,16 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
             link_start[k + 1] = (int)(sph.size() / 4);
         }
     }
-    std::vector<float> box((size_t)n_obs * 8);
+    // per box four float4: centre, half extents, lower corner, upper corner (w unused)
+    std::vector<float> box((size_t)n_obs * 16, 0.f);
     for (int o = 0; o < n_obs; ++o) {
         for (int c = 0; c < 3; ++c) {
-            box[8 * o + c] = (float)boxes[6 * o + c];
-            box[8 * o + 4 + c] = (float)boxes[6 * o + 3 + c];
+            const double ctr = boxes[6 * o + c], ext = boxes[6 * o + 3 + c];
+            box[16 * o + c] = (float)ctr;
+            box[16 * o + 4 + c] = (float)ext;
+            box[16 * o + 8 + c] = (float)(ctr - ext);
+            box[16 * o + 12 + c] = (float)(ctr + ext);
         }
-        box[8 * o + 3] = 0.f;
-        box[8 * o + 7] = 0.f;
     }
     auto pack_poses = [&](const double *src, std::vector<float> &dst) {
         dst.assign((size_t)B * 8, 0.f);

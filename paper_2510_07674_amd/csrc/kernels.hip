@@ -224,56 +224,69 @@ __device__ __forceinline__ void contact(int phase, float wgt, float cx, float cy
     }
 }
 
-template <bool GRAD, int CH>
-__device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
-                                              const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
-                                              bool act, float &cost, float &viol, float (&wf)[3], float (&wt)[3])
+// Axis-aligned bounds of one lane's sphere chunk with a 1e-4 m margin against rounding;
+// empty for inactive lanes.
+struct LaneBox {
+    float lo0, lo1, lo2, hi0, hi1, hi2;
+};
+template <int CH>
+__device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (&cy)[CH], const float (&cz)[CH],
+                                            const float (&r)[CH], bool act)
 {
-    float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    LaneBox b{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     if (act) {
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            lo0 = fminf(lo0, cx[i] - r[i]);
-            lo1 = fminf(lo1, cy[i] - r[i]);
-            lo2 = fminf(lo2, cz[i] - r[i]);
-            hi0 = fmaxf(hi0, cx[i] + r[i]);
-            hi1 = fmaxf(hi1, cy[i] + r[i]);
-            hi2 = fmaxf(hi2, cz[i] + r[i]);
+            b.lo0 = fminf(b.lo0, cx[i] - r[i]);
+            b.lo1 = fminf(b.lo1, cy[i] - r[i]);
+            b.lo2 = fminf(b.lo2, cz[i] - r[i]);
+            b.hi0 = fmaxf(b.hi0, cx[i] + r[i]);
+            b.hi1 = fmaxf(b.hi1, cy[i] + r[i]);
+            b.hi2 = fmaxf(b.hi2, cz[i] + r[i]);
         }
-        lo0 -= 1e-4f;
-        lo1 -= 1e-4f;
-        lo2 -= 1e-4f;
-        hi0 += 1e-4f;
-        hi1 += 1e-4f;
-        hi2 += 1e-4f;
+        b.lo0 -= 1e-4f;
+        b.lo1 -= 1e-4f;
+        b.lo2 -= 1e-4f;
+        b.hi0 += 1e-4f;
+        b.hi1 += 1e-4f;
+        b.hi2 += 1e-4f;
     }
-    lo0 = uniform(wave_min(lo0));
-    lo1 = uniform(wave_min(lo1));
-    lo2 = uniform(wave_min(lo2));
-    hi0 = uniform(wave_max(hi0));
-    hi1 = uniform(wave_max(hi1));
-    hi2 = uniform(wave_max(hi2));
+    return b;
+}
+
+template <bool GRAD, int CH>
+__device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
+                                              const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
+                                              const LaneBox &lb, bool act, float &cost, float &viol, float (&wf)[3],
+                                              float (&wt)[3])
+{
+    const float lo0 = uniform(wave_min(lb.lo0)), lo1 = uniform(wave_min(lb.lo1)), lo2 = uniform(wave_min(lb.lo2));
+    const float hi0 = uniform(wave_max(lb.hi0)), hi1 = uniform(wave_max(lb.hi1)), hi2 = uniform(wave_max(lb.hi2));
     const int lane = threadIdx.x & 63;
     for (int base = 0; base < P.O; base += 64) {
         const int ol = base + lane;
         bool ov = false;
         if (ol < P.O) {
-            const float4 bc = ldc(P.box, 2 * ol), be = ldc(P.box, 2 * ol + 1);
-            ov = bc.x - be.x <= hi0 && bc.x + be.x >= lo0 && bc.y - be.y <= hi1 && bc.y + be.y >= lo1 &&
-                 bc.z - be.z <= hi2 && bc.z + be.z >= lo2;
+            const float4 bl = ldc(P.box, 4 * ol + 2), bh = ldc(P.box, 4 * ol + 3);
+            ov = bl.x <= hi0 && bh.x >= lo0 && bl.y <= hi1 && bh.y >= lo1 && bl.z <= hi2 && bh.z >= lo2;
         }
         unsigned long long m = __ballot(ov);
         while (m) {
             const int o = base + __builtin_ctzll(m);
             m &= m - 1;
-            const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
+            // lane pretest: the lane's own bounds against the obstacle
+            const float4 bl = ldc(P.box, 4 * o + 2), bh = ldc(P.box, 4 * o + 3);
+            const bool lp = lb.lo0 <= bh.x && lb.hi0 >= bl.x && lb.lo1 <= bh.y && lb.hi1 >= bl.y &&
+                            lb.lo2 <= bh.z && lb.hi2 >= bl.z;
+            if (!__ballot(lp)) continue;
+            const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
             unsigned long long hm[CH], any = 0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const float ux = fabsf(cx[i] - bc.x) - be.x;
                 const float uy = fabsf(cy[i] - bc.y) - be.y;
                 const float uz = fabsf(cz[i] - bc.z) - be.z;
-                hm[i] = __ballot(act && fmaxf(fmaxf(ux, uy), uz) < r[i]);
+                hm[i] = __ballot(lp && fmaxf(fmaxf(ux, uy), uz) < r[i]);
                 any |= hm[i];
             }
             if (!any) continue;
@@ -297,17 +310,21 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
 template <bool GRAD, int CH>
 __device__ __forceinline__ void collide_blocks(const KProb &P, int phase, float wgt, const float (&cx)[CH],
                                                const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
-                                               bool act, int b, bool own_visible, const float *s_pose,
-                                               float *s_pacc, float &cost, float &viol, float (&wf)[3],
-                                               float (&wt)[3])
+                                               const LaneBox &lb, bool act, int b, bool own_visible,
+                                               const float *s_pose, float *s_pacc, float &cost, float &viol,
+                                               float (&wf)[3], float (&wt)[3])
 {
     const int B = P.B;
     const float half = P.half;
     for (int bb = 0; bb < B; ++bb) {
         const bool movable = bb < b;
-        const bool vis = act && (bb != b || own_visible);
         const float *pp = s_pose + ((movable ? 0 : MAX_B) + bb) * 8;
-        const float tx = pp[0], ty = pp[1], tz = pp[2], cs = pp[4], sn = pp[5];
+        const float tx = pp[0], ty = pp[1], tz = pp[2], cs = pp[4], sn = pp[5], ext = pp[6];
+        // lane pretest against the block's axis-aligned bounds (xy half extent of the
+        // yawed square in pp[6])
+        const bool vis = act && (bb != b || own_visible) && tx - ext <= lb.hi0 && tx + ext >= lb.lo0 &&
+                         ty - ext <= lb.hi1 && ty + ext >= lb.lo1 && tz - half <= lb.hi2 && tz + half >= lb.lo2;
+        if (!__ballot(vis)) continue;
         unsigned long long hm[CH], any = 0;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
@@ -380,7 +397,7 @@ __device__ __forceinline__ void place_lane(const KProb &P, int phase, int i, int
     const float dyx = -si * sbx - ci * sby, dyy = ci * sbx - si * sby;  // d c / d yaw
 
     for (int o = 0; o < P.O; ++o) {
-        const float4 bc = ldc(P.box, 2 * o), be = ldc(P.box, 2 * o + 1);
+        const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
         const float dx = cx - bc.x, dy = cy - bc.y, dz = cz - bc.z;
         const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
         if (fmaxf(fmaxf(ux, uy), uz) < rb) {
@@ -665,9 +682,10 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
             cz[i] = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
             r[i] = sp.w;
         }
-        collide_boxes<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, sl.active, cost, viol, wf, wt);
-        collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, sl.active, sl.b, own_vis, s_pose, s_pacc,
-                                 cost, viol, wf, wt);
+        const LaneBox lb = lane_box<CH>(cx, cy, cz, r, sl.active);
+        collide_boxes<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, cost, viol, wf, wt);
+        collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, sl.b, own_vis, s_pose,
+                                 s_pacc, cost, viol, wf, wt);
     }
     wr[0] = wt[0]; wr[1] = wt[1]; wr[2] = wt[2];
     wr[3] = wf[0]; wr[4] = wf[1]; wr[5] = wf[2];
@@ -731,9 +749,17 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
             r[k] = rb;
         }
         const float w_block = P.w[W_BLOCK];
-        collide_boxes<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, held, cost, viol, ef, et);
-        collide_blocks<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, held, sl.b, false, s_pose, s_pacc, cost, viol,
-                                ef, et);
+        // bounds of the eight spheres: centre +- (so * row sums of |R_B| + rb)
+        LaneBox lb{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        if (held) {
+            const float e0 = so * (fabsf(RB[0][0]) + fabsf(RB[0][1]) + fabsf(RB[0][2])) + rb + 1e-4f;
+            const float e1 = so * (fabsf(RB[1][0]) + fabsf(RB[1][1]) + fabsf(RB[1][2])) + rb + 1e-4f;
+            const float e2 = so * (fabsf(RB[2][0]) + fabsf(RB[2][1]) + fabsf(RB[2][2])) + rb + 1e-4f;
+            lb = LaneBox{tb0 - e0, tb1 - e1, tb2 - e2, tb0 + e0, tb1 + e1, tb2 + e2};
+        }
+        collide_boxes<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, lb, held, cost, viol, ef, et);
+        collide_blocks<GRAD, 8>(P, phase, w_block, cx, cy, cz, r, lb, held, sl.b, false, s_pose, s_pacc, cost,
+                                viol, ef, et);
     }
     // grasp alignment at the first transfer waypoint (C_start: position, roll/pitch)
     if (sl.active && sl.tau == 1 && sl.w == 0) {
@@ -859,7 +885,8 @@ __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const S
     }
 }
 
-__device__ __forceinline__ void set_pose_entry(float *s_pose, int b, float x, float y, float z, float yaw)
+// Pose table entry: x, y, z, yaw, cos, sin, and the xy half extent of the yawed square.
+__device__ __forceinline__ void set_pose_entry(float *s_pose, int b, float x, float y, float z, float yaw, float half)
 {
     float s, c;
     sincosf(yaw, &s, &c);
@@ -870,6 +897,7 @@ __device__ __forceinline__ void set_pose_entry(float *s_pose, int b, float x, fl
     pp[3] = yaw;
     pp[4] = c;
     pp[5] = s;
+    pp[6] = half * (fabsf(c) + fabsf(s));
 }
 
 __device__ __forceinline__ float adam_update(float x, float &m, float &v, float g, float lr, float b1, float b2,
@@ -916,7 +944,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     for (int j = 0; j < NJ; ++j) q[j] = sl.active ? a.q_in[qoff + j] : 0.f;
     if (tid < B) {
         const float *pi = a.pose_in + ((size_t)p * B + tid) * 4;
-        set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3]);
+        set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3], P.half);
     } else if (tid < 2 * B) {  // blockDim >= 64 >= 2 * MAX_B
         const int b = tid - B;
         const float4 a0 = ldc(P.blk_init, 2 * b), a1 = ldc(P.blk_init, 2 * b + 1);
@@ -927,6 +955,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
         pp[3] = a0.w;
         pp[4] = a1.x;
         pp[5] = a1.y;
+        pp[6] = P.half * (fabsf(a1.x) + fabsf(a1.y));
     }
     float *s_pacc_w = s_pacc + wave * MAX_B * 4;
     if (lane < 4 * B) s_pacc_w[lane] = 0.f;
@@ -990,6 +1019,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                     sincosf(x, &s, &cc);
                     s_pose[bb * 8 + 4] = cc;
                     s_pose[bb * 8 + 5] = s;
+                    s_pose[bb * 8 + 6] = P.half * (fabsf(cc) + fabsf(s));
                 }
             }
             __syncthreads();
