@@ -86,6 +86,7 @@ typedef struct {
     double eta1, alpha1;
     double lin_frac2, eta2, alpha2, beta1, beta2, adam_eps;
     int32_t ik_iters;
+    int32_t ik_restarts;  /* IK starts per (particle, block) in the lift, 1..8 */
     double ik_lambda, ik_noise, mid_noise;
     double sat_eps;   /* a particle satisfies the constraints when its violation < sat_eps */
     int32_t retries;  /* stage-1 resampling rounds when nothing satisfies */
@@ -184,9 +185,14 @@ int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, 
  * spasm_ik_iterate: n independent solves, in place on d_q [n][7], kind 0 = grasp (block
  *   origin to target xyz, block z axis up, yaw free), kind 1 = place (x, y, z, yaw);
  *   d_target [n][4].
- * spasm_ik_lift: per particle and block, start at q_home + ik_noise U[-1,1]^7 (counter
- *   (particle, 2b + chunk, 0, 2)), grasp at block_init[b], then place at d_pose[p][b]
- *   starting from the grasp solution.  d_qgrasp, d_qplace [P][B][7]. */
+ * spasm_ik_lift: per particle and block, ik_restarts multi-start solves.  Grasp at
+ *   block_init[b]: start 0 at q_home + ik_noise U[-1,1]^7 (counter (particle, 2b + chunk,
+ *   0, 2)), start r >= 1 uniform over the limits (counter (particle, 2b + chunk, r, 2)).
+ *   Place at d_pose[p][b]: start 0 from the chosen grasp solution, start r >= 1 uniform
+ *   (counter (particle, 2B + 2b + chunk, r, 2)).  Each solve keeps the first start whose
+ *   final error |e| (position and orientation error of the iteration) is below 1e-4,
+ *   otherwise the start with the smallest error (the first on ties).
+ *   d_qgrasp, d_qplace [P][B][7]. */
 int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d_target, float *d_q,
                      int32_t iters, void *stream);
 int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose, uint64_t seed, int32_t iters,

@@ -70,7 +70,9 @@ def lib():
         L.or_argsort.argtypes = [i, vp, vp]
         L.or_order.argtypes = [i, vp, vp, d, vp, vp]
         L.or_ik_iterate.argtypes = [P, i, vp, vp, i, d]
-        L.or_ik_lift.argtypes = [P, i, vp, u64, i, d, d, vp, vp]
+        L.or_ik_lift.argtypes = [P, i, vp, u64, i, d, d, i, vp, vp]
+        L.or_ik_error.argtypes = [P, i, vp, vp]
+        L.or_ik_error.restype = d
         L.or_traj_init.argtypes = [P, i, i, vp, vp, u64, d, vp]
         L.or_stage1.argtypes = [P, i, i, u64, i, i, i, d, d, vp, vp, vp]
         L.or_stage2.argtypes = [P, i, i, i, i, d, d, d, d, d, vp, vp]
@@ -183,13 +185,17 @@ class Oracle:
         lib().or_ik_iterate(self.ref, kind, _ptr(_f64(target)), _ptr(q), iters, self.params.ik_lambda)
         return q
 
+    def ik_error(self, kind, target, q):
+        """|e| of the IK iteration at q (position and orientation error of the block frame)."""
+        return lib().or_ik_error(self.ref, kind, _ptr(_f64(target)), _ptr(_f64(q)))
+
     def ik_lift(self, pose, seed, iters=None):
         pose = _f64(pose)
         P, B = pose.shape[:2]
         qg, qp = np.zeros((P, B, 7)), np.zeros((P, B, 7))
         pr = self.params
         lib().or_ik_lift(self.ref, P, _ptr(pose), seed, pr.ik_iters if iters is None else iters,
-                         pr.ik_lambda, pr.ik_noise, _ptr(qg), _ptr(qp))
+                         pr.ik_lambda, pr.ik_noise, pr.ik_restarts, _ptr(qg), _ptr(qp))
         return qg, qp
 
     def traj_init(self, qg, qp, W, seed):

@@ -784,49 +784,65 @@ static void solve6(double A[6][6], double *b)
     }
 }
 
-void or_ik_iterate(const or_problem *pb, int kind, const double *target, double *q, int iters, double lambda)
+/* IK error of the block frame T_B = T_E G^-1 at q: position error, then the
+ * orientation error (kind 0: z axis against e_z; kind 1: half the sum of the axis cross
+ * products against Rz(yaw)).  J (optional) receives the 6x7 geometric Jacobian of T_B. */
+static void ik_error(const or_problem *pb, int kind, const double *target, const double *q, double e[6],
+                     double J[6][NJ])
 {
     const double *G = pb->grasp;
-    frame Gi;
+    frame Gi, F[9], TB;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Gi.R[3 * i + j] = G[4 * j + i];
     for (int i = 0; i < 3; ++i) Gi.p[i] = -(Gi.R[3 * i] * G[3] + Gi.R[3 * i + 1] * G[7] + Gi.R[3 * i + 2] * G[11]);
+    fk_frames(pb, q, F);
+    compose(&F[8], &Gi, &TB);
+    for (int i = 0; i < 3; ++i) e[i] = target[i] - TB.p[i];
+    double ew[3] = {0, 0, 0};
+    if (kind == 0) {
+        double u[3], ez[3] = {0, 0, 1};
+        col(&TB, 2, u);
+        cross3(u, ez, ew);
+    } else {
+        double c = cos(target[3]), s = sin(target[3]);
+        double Rt[3][3] = {{c, -s, 0}, {s, c, 0}, {0, 0, 1}};
+        for (int a = 0; a < 3; ++a) {
+            double u[3], v[3] = {Rt[0][a], Rt[1][a], Rt[2][a]}, t[3];
+            col(&TB, a, u);
+            cross3(u, v, t);
+            for (int i = 0; i < 3; ++i) ew[i] += 0.5 * t[i];
+        }
+    }
+    e[3] = ew[0];
+    e[4] = ew[1];
+    e[5] = ew[2];
+    if (!J) return;
+    for (int j = 1; j <= NJ; ++j) {
+        double z[3], r[3], t[3];
+        col(&F[j - 1], 2, z);
+        for (int i = 0; i < 3; ++i) r[i] = TB.p[i] - F[j - 1].p[i];
+        cross3(z, r, t);
+        for (int i = 0; i < 3; ++i) {
+            J[i][j - 1] = t[i];
+            J[3 + i][j - 1] = z[i];
+        }
+    }
+}
+
+double or_ik_error(const or_problem *pb, int kind, const double *target, const double *q)
+{
+    double e[6];
+    ik_error(pb, kind, target, q, e, NULL);
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i) s += e[i] * e[i];
+    return sqrt(s);
+}
+
+void or_ik_iterate(const or_problem *pb, int kind, const double *target, double *q, int iters, double lambda)
+{
     for (int it = 0; it < iters; ++it) {
-        frame F[9], TB;
-        fk_frames(pb, q, F);
-        compose(&F[8], &Gi, &TB);
-        double e[6];
-        for (int i = 0; i < 3; ++i) e[i] = target[i] - TB.p[i];
-        double ew[3] = {0, 0, 0};
-        if (kind == 0) {
-            double u[3], ez[3] = {0, 0, 1};
-            col(&TB, 2, u);
-            cross3(u, ez, ew);
-        } else {
-            double c = cos(target[3]), s = sin(target[3]);
-            double Rt[3][3] = {{c, -s, 0}, {s, c, 0}, {0, 0, 1}};
-            for (int a = 0; a < 3; ++a) {
-                double u[3], v[3] = {Rt[0][a], Rt[1][a], Rt[2][a]}, t[3];
-                col(&TB, a, u);
-                cross3(u, v, t);
-                for (int i = 0; i < 3; ++i) ew[i] += 0.5 * t[i];
-            }
-        }
-        e[3] = ew[0];
-        e[4] = ew[1];
-        e[5] = ew[2];
-        double J[6][NJ];
-        for (int j = 1; j <= NJ; ++j) {
-            double z[3], r[3], t[3];
-            col(&F[j - 1], 2, z);
-            for (int i = 0; i < 3; ++i) r[i] = TB.p[i] - F[j - 1].p[i];
-            cross3(z, r, t);
-            for (int i = 0; i < 3; ++i) {
-                J[i][j - 1] = t[i];
-                J[3 + i][j - 1] = z[i];
-            }
-        }
-        double A[6][6];
+        double e[6], J[6][NJ], A[6][6];
+        ik_error(pb, kind, target, q, e, J);
         for (int r = 0; r < 6; ++r)
             for (int c = 0; c < 6; ++c) {
                 double s = 0.0;
@@ -842,26 +858,56 @@ void or_ik_iterate(const or_problem *pb, int kind, const double *target, double 
     }
 }
 
-/* Per particle and block: start at q_home + noise (counter (particle, 2b + chunk, 0,
- * stream 2)), solve the grasp, then the placement starting from the grasp solution. */
+/* One multi-start solve: start 0 is q0, start r >= 1 is uniform over the joint limits
+ * (counter (particle, sub, r, stream 2) and (particle, sub + 1, r, stream 2)).  The
+ * result is the first start whose final error is below OR_IK_ACCEPT, otherwise the
+ * start with the smallest error (the first one on ties). */
+#define OR_IK_ACCEPT 1e-4
+static void ik_multistart(const or_problem *pb, int kind, const double *target, const double *q0, uint64_t seed,
+                          int p, int sub, int restarts, int iters, double lambda, double *q_out)
+{
+    double best = INFINITY;
+    for (int r = 0; r < restarts; ++r) {
+        double q[NJ];
+        if (r == 0) {
+            for (int j = 0; j < NJ; ++j) q[j] = q0[j];
+        } else {
+            double u[8];
+            uniforms4(seed, (uint64_t)p, (uint64_t)sub, (uint64_t)r, STREAM_IK, u);
+            uniforms4(seed, (uint64_t)p, (uint64_t)(sub + 1), (uint64_t)r, STREAM_IK, u + 4);
+            for (int j = 0; j < NJ; ++j) q[j] = pb->lo[j] + (pb->hi[j] - pb->lo[j]) * u[j];
+        }
+        or_ik_iterate(pb, kind, target, q, iters, lambda);
+        const double err = or_ik_error(pb, kind, target, q);
+        if (err < best) {
+            best = err;
+            for (int j = 0; j < NJ; ++j) q_out[j] = q[j];
+        }
+        if (err < OR_IK_ACCEPT) break;
+    }
+}
+
+/* Per particle and block (Sec. III-B lift): the grasp at block_init[b] from q_home +
+ * noise U[-1,1]^7 (counter (particle, 2b + chunk, 0, stream 2)) and restarts drawn at
+ * sub-index 2b; then the placement at pose[p][b] from the grasp solution, restarts at
+ * sub-index 2B + 2b. */
 void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, int iters, double lambda,
-                double noise, double *q_grasp, double *q_place)
+                double noise, int restarts, double *q_grasp, double *q_place)
 {
     const int B = pb->B;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int p = 0; p < P; ++p)
         for (int b = 0; b < B; ++b) {
-            double u[8], q[NJ];
+            double u[8], q0[NJ];
             uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b), 0, STREAM_IK, u);
             uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b + 1), 0, STREAM_IK, u + 4);
             for (int j = 0; j < NJ; ++j)
-                q[j] = clampd(pb->q_home[j] + noise * (2.0 * u[j] - 1.0), pb->lo[j], pb->hi[j]);
-            or_ik_iterate(pb, 0, pb->block_init + 4 * b, q, iters, lambda);
+                q0[j] = clampd(pb->q_home[j] + noise * (2.0 * u[j] - 1.0), pb->lo[j], pb->hi[j]);
             double *g = q_grasp + ((size_t)p * B + b) * NJ;
-            for (int j = 0; j < NJ; ++j) g[j] = q[j];
-            or_ik_iterate(pb, 1, pose + ((size_t)p * B + b) * 4, q, iters, lambda);
+            ik_multistart(pb, 0, pb->block_init + 4 * b, q0, seed, p, 2 * b, restarts, iters, lambda, g);
             double *pl = q_place + ((size_t)p * B + b) * NJ;
-            for (int j = 0; j < NJ; ++j) pl[j] = q[j];
+            ik_multistart(pb, 1, pose + ((size_t)p * B + b) * 4, g, seed, p, 2 * B + 2 * b, restarts, iters,
+                          lambda, pl);
         }
 }
 

@@ -1201,58 +1201,80 @@ __global__ __launch_bounds__(1024) void k_sort(int kind, int n, const float *cos
 // ------------------------------------------------------------------------------------
 // Lift (damped least squares on the block frame) and trajectory seeding.
 // ------------------------------------------------------------------------------------
+// IK error of the block frame T_B = T_E G^-1 at q (position, then orientation: kind 0
+// the z axis against e_z, kind 1 half the sum of axis cross products against Rz(yaw)),
+// with the joint origins and axes o_{j-1}, z_{j-1} and the block origin for the Jacobian.
+__device__ __forceinline__ void ik_eval(const KProb &P, int kind, float tx, float ty, float tz, float cy, float sy,
+                                        const float (&q)[NJ], float (&ax)[NJ][6], float &t0, float &t1, float &t2,
+                                        float (&e)[6])
+{
+    Frame F;
+    frame_identity(F);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        ax[j][0] = F.p0; ax[j][1] = F.p1; ax[j][2] = F.p2;
+        ax[j][3] = F.z0; ax[j][4] = F.z1; ax[j][5] = F.z2;
+        dh_step(F, P.a[j], P.d[j], P.ca[j], P.sa[j], q[j]);
+    }
+    const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
+    const float *Gr = P.Gi_R;
+    float RB[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        RB[0][c] = Gr[c] * F.x0 + Gr[3 + c] * F.y0 + Gr[6 + c] * F.z0;
+        RB[1][c] = Gr[c] * F.x1 + Gr[3 + c] * F.y1 + Gr[6 + c] * F.z1;
+        RB[2][c] = Gr[c] * F.x2 + Gr[3 + c] * F.y2 + Gr[6 + c] * F.z2;
+    }
+    t0 = pe0 + P.Gi_t[0] * F.x0 + P.Gi_t[1] * F.y0 + P.Gi_t[2] * F.z0;
+    t1 = pe1 + P.Gi_t[0] * F.x1 + P.Gi_t[1] * F.y1 + P.Gi_t[2] * F.z1;
+    t2 = pe2 + P.Gi_t[0] * F.x2 + P.Gi_t[1] * F.y2 + P.Gi_t[2] * F.z2;
+    e[0] = tx - t0;
+    e[1] = ty - t1;
+    e[2] = tz - t2;
+    if (kind == 0) {
+        // (R_B e_z) x e_z
+        e[3] = RB[1][2];
+        e[4] = -RB[0][2];
+        e[5] = 0.f;
+    } else {
+        // 1/2 sum_c (R_B e_c) x (Rz(yaw) e_c)
+        const float R0[3] = {cy, sy, 0.f}, R1[3] = {-sy, cy, 0.f};
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        w0 += RB[1][0] * R0[2] - RB[2][0] * R0[1];
+        w1 += RB[2][0] * R0[0] - RB[0][0] * R0[2];
+        w2 += RB[0][0] * R0[1] - RB[1][0] * R0[0];
+        w0 += RB[1][1] * R1[2] - RB[2][1] * R1[1];
+        w1 += RB[2][1] * R1[0] - RB[0][1] * R1[2];
+        w2 += RB[0][1] * R1[1] - RB[1][1] * R1[0];
+        w0 += RB[1][2];   // (R_B e_z) x e_z
+        w1 += -RB[0][2];
+        e[3] = 0.5f * w0;
+        e[4] = 0.5f * w1;
+        e[5] = 0.5f * w2;
+    }
+}
+
+__device__ __forceinline__ float ik_error(const KProb &P, int kind, float tx, float ty, float tz, float tyaw,
+                                          const float (&q)[NJ])
+{
+    float sy, cy;
+    sincosf(tyaw, &sy, &cy);
+    float ax[NJ][6], t0, t1, t2, e[6];
+    ik_eval(P, kind, tx, ty, tz, cy, sy, q, ax, t0, t1, t2, e);
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) s += e[r] * e[r];
+    return sqrtf(s);
+}
+
 __device__ __forceinline__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ], int iters)
 {
     float sy, cy;
     sincosf(tyaw, &sy, &cy);
     const float lam2 = P.ik_lambda * P.ik_lambda;
     for (int it = 0; it < iters; ++it) {
-        float ax[NJ][6];  // o_{j-1}, z_{j-1}
-        Frame F;
-        frame_identity(F);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            ax[j][0] = F.p0; ax[j][1] = F.p1; ax[j][2] = F.p2;
-            ax[j][3] = F.z0; ax[j][4] = F.z1; ax[j][5] = F.z2;
-            dh_step(F, P.a[j], P.d[j], P.ca[j], P.sa[j], q[j]);
-        }
-        const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
-        const float *Gr = P.Gi_R;
-        float RB[3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            RB[0][c] = Gr[c] * F.x0 + Gr[3 + c] * F.y0 + Gr[6 + c] * F.z0;
-            RB[1][c] = Gr[c] * F.x1 + Gr[3 + c] * F.y1 + Gr[6 + c] * F.z1;
-            RB[2][c] = Gr[c] * F.x2 + Gr[3 + c] * F.y2 + Gr[6 + c] * F.z2;
-        }
-        const float t0 = pe0 + P.Gi_t[0] * F.x0 + P.Gi_t[1] * F.y0 + P.Gi_t[2] * F.z0;
-        const float t1 = pe1 + P.Gi_t[0] * F.x1 + P.Gi_t[1] * F.y1 + P.Gi_t[2] * F.z1;
-        const float t2 = pe2 + P.Gi_t[0] * F.x2 + P.Gi_t[1] * F.y2 + P.Gi_t[2] * F.z2;
-        float e[6];
-        e[0] = tx - t0;
-        e[1] = ty - t1;
-        e[2] = tz - t2;
-        if (kind == 0) {
-            // (R_B e_z) x e_z
-            e[3] = RB[1][2];
-            e[4] = -RB[0][2];
-            e[5] = 0.f;
-        } else {
-            // 1/2 sum_c (R_B e_c) x (Rz(yaw) e_c)
-            const float R0[3] = {cy, sy, 0.f}, R1[3] = {-sy, cy, 0.f};
-            float w0 = 0.f, w1 = 0.f, w2 = 0.f;
-            w0 += RB[1][0] * R0[2] - RB[2][0] * R0[1];
-            w1 += RB[2][0] * R0[0] - RB[0][0] * R0[2];
-            w2 += RB[0][0] * R0[1] - RB[1][0] * R0[0];
-            w0 += RB[1][1] * R1[2] - RB[2][1] * R1[1];
-            w1 += RB[2][1] * R1[0] - RB[0][1] * R1[2];
-            w2 += RB[0][1] * R1[1] - RB[1][1] * R1[0];
-            w0 += RB[1][2];   // (R_B e_z) x e_z
-            w1 += -RB[0][2];
-            e[3] = 0.5f * w0;
-            e[4] = 0.5f * w1;
-            e[5] = 0.5f * w2;
-        }
+        float ax[NJ][6], t0, t1, t2, e[6];
+        ik_eval(P, kind, tx, ty, tz, cy, sy, q, ax, t0, t1, t2, e);
         // A = J J^T + lambda^2 I, J column j = (z x (t_B - o), z)
         float A[6][6];
 #pragma unroll
@@ -1329,26 +1351,66 @@ __global__ void k_ik_iterate(KProb P, int kind, int n, const float *target, floa
     for (int j = 0; j < NJ; ++j) qio[(size_t)gid * NJ + j] = q[j];
 }
 
-__global__ void k_ik_lift(KProb P, int nP, const float *pose, uint64_t seed, int iters, float *qg, float *qp)
+// Multi-start lift: eight lanes per (particle, block), lane r runs start r < restarts
+// (start 0 from q_home + noise, resp. from the chosen grasp; the others uniform over the
+// limits).  The group keeps the first start whose error is below 1e-4, otherwise the
+// smallest error (first on ties), and broadcasts it to the group.
+__device__ __forceinline__ int ik_pick(float err, int r, int restarts)
+{
+    const int lane = threadIdx.x & 63, g0 = lane & ~7;
+    const unsigned long long acc = (__ballot(r < restarts && err < 1e-4f) >> g0) & 0xFFull;
+    if (acc) return g0 + __builtin_ctzll(acc);
+    const float e = r < restarts ? err : INFINITY;
+    const float m = group8_reduce(e, OpMin());
+    const unsigned long long at = (__ballot(e == m) >> g0) & 0xFFull;
+    return g0 + __builtin_ctzll(at);
+}
+
+__global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *pose, uint64_t seed, int iters,
+                                                 float *qg, float *qp)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nP * P.B) return;
-    const int p = gid / P.B, b = gid % P.B;
-    float u[8];
-    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b), 0, 2u, u);
-    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b + 1), 0, 2u, u + 4);
-    float q[NJ];
+    const int grp = gid >> 3, r = gid & 7;
+    if (grp >= nP * P.B) return;  // whole 8-lane groups only
+    const int B = P.B, p = grp / B, b = grp % B, R = P.ik_restarts;
+    float u[8], q[NJ];
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b), (uint64_t)r, 2u, u);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * b + 1), (uint64_t)r, 2u, u + 4);
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
-        q[j] = fminf(fmaxf(P.q_home[j] + P.ik_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
+        q[j] = r == 0 ? fminf(fmaxf(P.q_home[j] + P.ik_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j])
+                      : P.lo[j] + (P.hi[j] - P.lo[j]) * u[j];
     const float4 I = ldc(P.blk_init, 2 * b);
-    ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
+    float err = INFINITY;
+    if (r < R) {
+        ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
+        err = ik_error(P, 0, I.x, I.y, I.z, 0.f, q);
+    }
+    int src = ik_pick(err, r, R);
+    float qc[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) qg[(size_t)gid * NJ + j] = q[j];
-    const float *t = pose + (size_t)gid * 4;
-    ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
+    for (int j = 0; j < NJ; ++j) qc[j] = __shfl(q[j], src, 64);
+    if (r == 0) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) qp[(size_t)gid * NJ + j] = q[j];
+        for (int j = 0; j < NJ; ++j) qg[(size_t)grp * NJ + j] = qc[j];
+    }
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * B + 2 * b), (uint64_t)r, 2u, u);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * B + 2 * b + 1), (uint64_t)r, 2u, u + 4);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) q[j] = r == 0 ? qc[j] : P.lo[j] + (P.hi[j] - P.lo[j]) * u[j];
+    const float *t = pose + (size_t)grp * 4;
+    err = INFINITY;
+    if (r < R) {
+        ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
+        err = ik_error(P, 1, t[0], t[1], t[2], t[3], q);
+    }
+    src = ik_pick(err, r, R);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qc[j] = __shfl(q[j], src, 64);
+    if (r == 0) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) qp[(size_t)grp * NJ + j] = qc[j];
+    }
 }
 
 __global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q)
@@ -1584,8 +1646,8 @@ hipError_t launch_ik_iterate(const KProb &P, int kind, int n, const float *targe
 hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t seed, int iters, float *qg, float *qp,
                           hipStream_t st)
 {
-    const int n = nP * P.B;
-    hipLaunchKernelGGL(k_ik_lift, dim3((n + 127) / 128), dim3(128), 0, st, P, nP, pose, seed, iters, qg, qp);
+    const long n = (long)nP * P.B * 8;
+    hipLaunchKernelGGL(k_ik_lift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, nP, pose, seed, iters, qg, qp);
     return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ class Params:
     adam_eps: float = 1e-8
     # lift / initialisation
     ik_iters: int = 50
+    ik_restarts: int = 8      # multi-start lift: starts per (particle, block)
     ik_lambda: float = 0.05
     ik_noise: float = 0.5
     mid_noise: float = 0.5

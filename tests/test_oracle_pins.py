@@ -698,3 +698,65 @@ def test_traj_init_closed_form(orc):
             # the intermediate waypoint is the endpoints' midpoint + noise within +-mid_noise
             qa = q[p, s, 0]
             assert np.all(np.abs(q[p, s, m] - 0.5 * (qa + end)) <= pr.mid_noise + 1e-12)
+
+
+def test_ik_lift_multistart_rule(orc):
+    """Multi-start lift, rebuilt by brute force: starts from numpy's Philox (counter
+    (particle, sub, start, 2), 24-bit uniforms), one IK solve per start, and the rule
+    'first start with error < 1e-4, else the smallest error (first on ties)'."""
+    prob, pr, _ = synth.config("tower4", 3)
+    o = orc.Oracle(prob, pr)
+    rng = np.random.default_rng(23)
+    P, B, seed = 4, prob.B, 11
+    pose = o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.05))
+    qg, qp = o.ik_lift(pose, seed=seed)
+
+    def u7(p, sub, r):
+        u = []
+        for k in (sub, sub + 1):  # numpy advances the counter before a block: use p - 1
+            raw = np.random.Philox(key=np.array([seed, 0], np.uint64),
+                                   counter=np.array([p - 1, k, r, 2], np.uint64)).random_raw(4)
+            u += list((raw >> np.uint64(40)).astype(np.float64) / 2.0**24)
+        return np.array(u[:7])
+
+    def pick(kind, target, starts):
+        best, qb = np.inf, None
+        for q0 in starts:
+            q = o.ik_iterate(kind, target, q0, pr.ik_iters)
+            e = o.ik_error(kind, target, q)
+            if e < best:
+                best, qb = e, q
+            if e < 1e-4:
+                break
+        return qb, best
+
+    n_acc = 0
+    for p in range(1, P):
+        for b in range(B):
+            s0 = np.clip(prob.q_home + pr.ik_noise * (2 * u7(p, 2 * b, 0) - 1), prob.lo, prob.hi)
+            starts = [s0] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * b, r) for r in range(1, pr.ik_restarts)]
+            g, eg = pick(0, prob.block_init[b], starts)
+            assert np.array_equal(g, qg[p, b])
+            starts = [g] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * B + 2 * b, r)
+                            for r in range(1, pr.ik_restarts)]
+            pl, ep = pick(1, pose[p, b], starts)
+            assert np.array_equal(pl, qp[p, b])
+            n_acc += (eg < 1e-4) + (ep < 1e-4)
+    assert n_acc > 0
+
+
+def test_ik_error_is_residual_norm(orc):
+    """ik_error at an exact solution of the scara chain is 0 and grows with the target
+    offset as the Euclidean norm of the position error (orientation already aligned)."""
+    prob = scara_problem(B=1)
+    o = orc.Oracle(prob, synth.Params())
+    q = np.array([0.3, -0.4, 0.2, 0.0, 0.0, 0.0, 0.0])
+    F = o.fk(q).reshape(9, 12)
+    R8, p8 = F[8, :9].reshape(3, 3), F[8, 9:]
+    G = prob.grasp
+    tB = R8 @ (-G[:, :3].T @ G[:, 3]) + p8
+    yaw = math.atan2((R8 @ G[:, :3].T)[1, 0], (R8 @ G[:, :3].T)[0, 0])
+    tgt = np.array([tB[0], tB[1], tB[2], yaw])
+    assert o.ik_error(1, tgt, q) < 1e-12 and o.ik_error(0, tgt, q) < 1e-12
+    d = np.array([0.003, -0.004, 0.0, 0.0])
+    assert abs(o.ik_error(0, tgt + d, q) - 0.005) < 1e-12
