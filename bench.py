@@ -96,9 +96,11 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.warmup + args.steps
+    seeds = synth.certified_seeds(args.workload)
+    seeds = [seeds[i % len(seeds)] for i in range(n)]
     probs = []
-    for i in range(n):
-        prob, pr, cfg = synth.config(args.workload, i)
+    for s in seeds:
+        prob, pr, cfg = synth.config(args.workload, s)
         probs.append(spasm.Problem(prob, pr))
     dev0 = probs[0]
     work = dev0.make_workspace(cfg)

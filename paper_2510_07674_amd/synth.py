@@ -20,12 +20,16 @@ available; these synthetic towers-in-clutter stand in for them:
   the tower live in a placement region in front of the robot, 0.2-0.55 m out;
 * axis-aligned box obstacles with sides ~ U[0.05, 0.3] m resting anywhere on the
   table, kept out of a square around the base and small squares around the blocks'
-  initial poses and around a hidden tower site, so that a placement exists.
+  initial poses and around a hidden tower site, so that a placement exists;
+* scene instances of a workload are the seeds listed by `certified_seeds` (every block's
+  grasp and every tower slot reachable, certified offline by the oracle's IK); this
+  module only reads that list.
 """
 from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -236,6 +240,22 @@ def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
                    sph_link=sph_link, sph_c=sph_c, sph_r=sph_r, boxes=boxes, h=h,
                    block_init=block_init, mode=mode, goal=goal, grasp=grasp,
                    table=np.array(REGION, dtype=np.float64))
+
+
+_SEEDS_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                           "reachable_seeds.txt")
+
+
+def certified_seeds(name: str) -> list:
+    """Scene seeds of a workload whose every block grasp and tower slot were found
+    reachable (list written by tests/golden/make_reachable_seeds.py).  Random chains
+    sometimes cannot reach a top-down grasp at all; those scenes are not instances."""
+    with open(_SEEDS_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if parts and parts[0] == name:
+                return [int(v) for v in parts[1:]]
+    raise KeyError(name)
 
 
 # The five workloads.  C1..C3 are solve configurations, C4 is the differentiable-cost
