@@ -79,12 +79,14 @@ class Problem:
 @dataclasses.dataclass
 class Params:
     # cost weights (the paper only says "scalar weights"): constraint terms dominate the
-    # smoothness objective so that the solution is feasible
-    w_stable: float = 1.0
-    w_height: float = 1.0
+    # smoothness objective so that the solution is feasible.  Squared residuals (height,
+    # grasp, tie) carry large weights so that near the 1e-3 success threshold their
+    # gradients are comparable with the unit-weight linear penetration terms.
+    w_stable: float = 10.0
+    w_height: float = 1000.0
     w_coll: float = 1.0
-    w_start: float = 10.0
-    w_tie: float = 10.0
+    w_start: float = 100.0
+    w_tie: float = 100.0
     w_arm: float = 1.0
     w_block: float = 1.0
     w_lim: float = 1.0

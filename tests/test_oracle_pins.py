@@ -287,7 +287,7 @@ def test_stability_hand_value(orc):
     for dx, yaw in [(0.01, 0.0), (0.04, 0.0), (0.07, 0.7), (-0.05, -1.2)]:
         x = np.array([[[0.6, 0.0, yaw], [0.6 + dx * math.cos(yaw), dx * math.sin(yaw), 0.0]]])
         c, v, g, _ = o.place_cost(x, phase=orc.LIN)
-        exp = max(abs(dx) - 0.025, 0.0)
+        exp = pr.w_stable * max(abs(dx) - 0.025, 0.0)
         # block-block penetration appears only when the blocks overlap in xy; they sit
         # at different heights and the sphere margin keeps stacked blocks apart
         assert c[0] == pytest.approx(exp, abs=1e-12)
