@@ -174,7 +174,9 @@ __device__ __forceinline__ float box_sdf(float dx, float dy, float dz, float ux,
     const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
     const float qq = qx * qx + qy * qy + qz * qz;
     if (qq > 0.f) {
-        const float n = sqrtf(qq), inv = 1.f / n;
+        // hardware reciprocal square root (about 1 ulp) instead of the correctly rounded
+        // sqrt and divide sequences; qq > 0 here
+        const float inv = __builtin_amdgcn_rsqf(qq), n = qq * inv;
         gx = sgnf(dx) * (qx * inv);
         gy = sgnf(dy) * (qy * inv);
         gz = sgnf(dz) * (qz * inv);
@@ -900,12 +902,14 @@ __device__ __forceinline__ void set_pose_entry(float *s_pose, int b, float x, fl
     pp[6] = half * (fabsf(c) + fabsf(s));
 }
 
-__device__ __forceinline__ float adam_update(float x, float &m, float &v, float g, float lr, float b1, float b2,
-                                             float eps, float bc1, float bc2s)
+// Adam (torch semantics): step = lr / (1 - b1^k), ibc2 = 1 / sqrt(1 - b2^k); the square
+// root and reciprocal use the hardware instructions (about 1 ulp).
+__device__ __forceinline__ float adam_update(float x, float &m, float &v, float g, float step, float b1, float b2,
+                                             float eps, float ibc2)
 {
     m = b1 * m + (1.f - b1) * g;
     v = b2 * v + (1.f - b2) * g * g;
-    return x - (lr / bc1) * m / (sqrtf(v) / bc2s + eps);
+    return x - step * m * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v) * ibc2 + eps);
 }
 
 // One particle per workgroup.  MODE 0: cost, 1: cost + gradient (optionally scaled per
@@ -989,6 +993,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                 for (int j = 0; j < NJ; ++j) s_tie[1][sl.s][j] = g[j];
             __syncthreads();
             const float bc1 = 1.f - powf(b1, (float)k), bc2s = sqrtf(1.f - powf(b2, (float)k));
+            const float step = lr / bc1, ibc2 = 1.f / bc2s;
             if (sl.active) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
@@ -998,7 +1003,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                     float &m = s_mv[(0 * NJ + j) * blockDim.x + tid];
                     float &v = s_mv[(1 * NJ + j) * blockDim.x + tid];
                     float mm = m, vv = v;
-                    q[j] = adam_update(q[j], mm, vv, gj, lr, b1, b2, eps, bc1, bc2s);
+                    q[j] = adam_update(q[j], mm, vv, gj, step, b1, b2, eps, ibc2);
                     m = mm;
                     v = vv;
                 }
@@ -1010,7 +1015,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                 gsum += s_placeg[bb * 4 + c];
                 gsum += s_tiepose[bb * 4 + c];
                 float mm = s_popt[0][tid], vv = s_popt[1][tid];
-                const float x = adam_update(s_pose[bb * 8 + c], mm, vv, gsum, lr, b1, b2, eps, bc1, bc2s);
+                const float x = adam_update(s_pose[bb * 8 + c], mm, vv, gsum, step, b1, b2, eps, ibc2);
                 s_popt[0][tid] = mm;
                 s_popt[1][tid] = vv;
                 s_pose[bb * 8 + c] = x;
