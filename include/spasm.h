@@ -217,29 +217,33 @@ int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work,
                 float *d_best_q, float *d_best_pose, spasm_result *out, void *stream);
 
 /* --- serving (continuous batching) --------------------------------------------------------
- * A server owns one device arena of hbm_budget bytes and max_slots solve slots on its own
- * stream.  Requests are queued by spasm_server_submit.  Each spasm_server_step:
+ * A server owns one device arena of hbm_budget bytes, max_slots solve slots, an
+ * admission stream and four class streams.  Requests are queued by spasm_server_submit.
+ * Each spasm_server_step:
  *   1. admits queued requests in arrival order while a slot is free and the request's
  *      footprint (spasm_server_footprint) fits in the arena, and runs their stage 1, lift
- *      and seeding;
- *   2. advances every admitted solve by up to iters_per_step stage-2 iterations in ONE
- *      launch per (waypoint slots, sphere chunk) class -- solves of different block
- *      counts, waypoint counts and clutter share a launch, each particle is a workgroup,
- *      and the state stays on the device between steps;
+ *      and seeding on the admission stream; they join the launches from the next step;
+ *   2. advances every ready solve by a chunk of stage-2 iterations in ONE launch per
+ *      (thread count, sphere chunk) class -- solves of different block counts, waypoint
+ *      counts and clutter share a launch, each particle is a workgroup, and the state stays
+ *      on the device between steps.  Classes run on separate streams and overlap.  The
+ *      slowest class (by measured time per iteration) advances iters_per_step iterations,
+ *      the others as many as fit the same time (at most 64 iters_per_step);
  *   3. finishes solves that reached K (final evaluation, best particle written to the
  *      d_best_q [2B][W][7] / d_best_pose [B][4] buffers given at submit time) and queues
  *      their completion records;
- * then synchronises its stream.  A request's result is the same whatever else is in the
- * batch (every particle runs the same code on its own state).  Not thread-safe: one
- * thread drives a server; the problem and output buffers of a request must stay valid
- * until its completion is polled.  spasm_server_submit returns SPASM_EBUSY when the
- * request can never fit (footprint > budget). */
+ * then synchronises its streams.  A request's result is the same whatever else is in the
+ * batch and however its iterations are chunked (every particle runs the same code on its
+ * own state).  Not thread-safe: one thread drives a server; the problem and output
+ * buffers of a request must stay valid until its completion is polled.
+ * spasm_server_submit returns SPASM_EBUSY when the request can never fit
+ * (footprint > budget). */
 typedef struct spasm_server_s *spasm_server;
 
 typedef struct {
     uint64_t req_id;
     int32_t status;      /* SPASM_OK, or the error that ended the request */
-    int32_t steps;       /* server steps between admission and completion */
+    int32_t steps;       /* server steps from admission (its prefix step) to completion */
     spasm_result result; /* per-request stage times are not measured (0) */
 } spasm_completion;
 

@@ -1,9 +1,13 @@
 // Continuous-batching solve server (host side): requests are admitted in arrival order
-// as slots and arena memory free up, every admitted solve advances a chunk of stage-2
-// iterations per step inside one batched launch per (waypoint slots, sphere chunk) class,
-// and finished solves are retired with a completion record.  Device state of a solve
-// (its workspace and Adam moments) lives in the server's arena from admission to
-// completion; nothing is copied back to the host except the 48-byte summary.
+// as slots and arena memory free up; an admitted request runs its prefix (stage 1, lift,
+// seeding) on the admission stream while the running solves advance, and from the next
+// step on it advances a chunk of stage-2 iterations per step inside one batched launch
+// per (thread count, sphere chunk) class.  Classes run on their own streams so that they
+// overlap on the device, and each class's chunk is sized from its measured time per
+// iteration so that a step takes about as long for every class: a small solve then
+// advances many iterations while a large one advances a few.  Finished solves are retired
+// with a completion record.  Device state of a solve (workspace and Adam moments) lives in
+// the server's arena from admission to completion; only a 48-byte summary is copied back.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -26,12 +30,18 @@ struct Request {
 
 struct Slot {
     bool used = false;
+    bool ready = false;  // prefix done: takes part in the class launches
     Request r{};
     size_t off = 0, bytes = 0, opt_off = 0;
     SolveLayout L{};
     int k_done = 0, k_next = 0, steps = 0;
     bool finishing = false;
 };
+
+constexpr int N_CLASS_STREAMS = 4;
+constexpr int MAX_CLASS_LAUNCHES = 64;  // timed class launches per step
+
+using ClassKey = std::pair<int, int>;  // (threads, sphere chunk)
 
 size_t opt_bytes(spasm_problem prob, const spasm_solve_config &c)
 {
@@ -47,7 +57,10 @@ size_t request_footprint(spasm_problem prob, const spasm_solve_config &c)
 
 struct spasm_server_s {
     int device = 0;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;                       // admission (prefix) work
+    hipStream_t cs[N_CLASS_STREAMS] = {};           // class launches and finishing work
+    hipEvent_t ev[2 * MAX_CLASS_LAUNCHES] = {};     // start / end of each class launch
+    std::map<ClassKey, double> ms_per_iter;         // measured, smoothed
     size_t budget = 0;
     char *arena = nullptr;
     int iters = 25;
@@ -91,6 +104,17 @@ struct spasm_server_s {
     void cleanup()
     {
         if (st) (void)hipStreamSynchronize(st);
+        for (auto &c : cs)
+            if (c) {
+                (void)hipStreamSynchronize(c);
+                (void)hipStreamDestroy(c);
+                c = nullptr;
+            }
+        for (auto &e : ev)
+            if (e) {
+                (void)hipEventDestroy(e);
+                e = nullptr;
+            }
         if (arena) (void)hipFree(arena);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
@@ -127,6 +151,8 @@ extern "C" int spasm_server_create(size_t hbm_budget, int32_t max_slots, int32_t
     s->slots.resize((size_t)max_slots);
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
+    for (int i = 0; i < N_CLASS_STREAMS && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&s->cs[i], hipStreamNonBlocking);
+    for (int i = 0; i < 2 * MAX_CLASS_LAUNCHES && e == hipSuccess; ++i) e = hipEventCreate(&s->ev[i]);
     if (e != hipSuccess) {
         s->cleanup();
         delete s;
@@ -162,8 +188,9 @@ extern "C" int spasm_server_submit(spasm_server srv, spasm_problem prob, const s
 extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n_pending)
 {
     if (!srv) return fail(SPASM_EINVAL, "server is NULL");
-    hipStream_t st = srv->st;
-    // 1. admission in arrival order
+    hipStream_t sa = srv->st;
+    // 1. admission in arrival order; the prefix runs on the admission stream
+    std::vector<int> admitted;
     while (!srv->pending.empty()) {
         int si = -1;
         for (size_t i = 0; i < srv->slots.size(); ++i)
@@ -178,6 +205,7 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         if (!srv->alloc(need, &off)) break;
         Slot &s = srv->slots[(size_t)si];
         s.used = true;
+        s.ready = false;
         s.r = r;
         s.off = off;
         s.bytes = need;
@@ -185,25 +213,44 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         s.opt_off = off + align256(s.L.total);
         s.k_done = 0;
         s.steps = 0;
+        s.finishing = false;
         srv->pending.pop_front();
-        int rc = enqueue_prefix(s.r.prob, s.r.cfg, srv->arena + s.off, s.L, st);
+        int rc = enqueue_prefix(s.r.prob, s.r.cfg, srv->arena + s.off, s.L, sa);
         if (rc) return rc;
-        SPASM_HIP(launch_zero(srv->arena + s.opt_off, opt_bytes(s.r.prob, s.r.cfg), st));
+        SPASM_HIP(launch_zero(srv->arena + s.opt_off, opt_bytes(s.r.prob, s.r.cfg), sa));
+        admitted.push_back(si);
     }
-    // 2. one batched launch per (thread count, sphere chunk) class
-    std::map<std::pair<int, int>, std::vector<int>> classes;
+    // 2. one batched launch per class of ready solves, each class on its own stream, with
+    //    a chunk of iterations sized from the class's measured time per iteration
+    std::map<ClassKey, std::vector<int>> classes;
     for (size_t i = 0; i < srv->slots.size(); ++i) {
         const Slot &s = srv->slots[i];
-        if (s.used) classes[{traj_threads(s.r.prob->kp.B, s.r.cfg.W), s.r.prob->kp.chunk}].push_back((int)i);
+        if (s.used && s.ready) classes[{traj_threads(s.r.prob->kp.B, s.r.cfg.W), s.r.prob->kp.chunk}].push_back((int)i);
     }
-    int nd = 0;
+    double slowest = 0.0;
     for (auto &cl : classes) {
+        auto it = srv->ms_per_iter.find(cl.first);
+        if (it != srv->ms_per_iter.end()) slowest = std::max(slowest, it->second);
+    }
+    const double step_ms = slowest * srv->iters;  // 0 until some class has been timed
+    struct Launch {
+        ClassKey key;
+        int stream, event, iters;
+    };
+    std::vector<Launch> launches;
+    int nd = 0, li = 0;
+    for (auto &cl : classes) {
+        int chunk = srv->iters;
+        auto it = srv->ms_per_iter.find(cl.first);
+        if (step_ms > 0.0 && it != srv->ms_per_iter.end() && it->second > 0.0)
+            chunk = (int)std::max(1.0, std::min(64.0 * srv->iters, std::floor(step_ms / it->second + 1e-6)));
         const int d0 = nd;
-        int first = 0;
+        int first = 0, most = 0;
         for (int i : cl.second) {
             Slot &s = srv->slots[(size_t)i];
             const spasm_solve_config &c = s.r.cfg;
-            const int k1 = std::min(c.K, s.k_done + srv->iters);
+            const int k1 = std::min(c.K, s.k_done + chunk);
+            most = std::max(most, k1 - s.k_done);
             s.finishing = k1 == c.K;
             s.k_next = k1;
             ServeSolve &d = srv->h_desc[nd++];
@@ -226,27 +273,52 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
             d.first = first;
             first += c.M;
         }
+        const int sidx = li % N_CLASS_STREAMS, eidx = li < MAX_CLASS_LAUNCHES ? li : -1;
+        hipStream_t cst = srv->cs[sidx];
         SPASM_HIP(hipMemcpyAsync(srv->d_desc + d0, srv->h_desc + d0, sizeof(ServeSolve) * (size_t)(nd - d0),
-                                 hipMemcpyHostToDevice, st));
-        SPASM_HIP(launch_serve(cl.first.second, cl.first.first, first, srv->d_desc + d0, nd - d0, st));
+                                 hipMemcpyHostToDevice, cst));
+        if (eidx >= 0) SPASM_HIP(hipEventRecord(srv->ev[2 * eidx], cst));
+        SPASM_HIP(launch_serve(cl.first.second, cl.first.first, first, srv->d_desc + d0, nd - d0, cst));
+        if (eidx >= 0) SPASM_HIP(hipEventRecord(srv->ev[2 * eidx + 1], cst));
+        launches.push_back({cl.first, sidx, eidx, most});
+        // 3. finish the solves of this class that reached K, on the same stream
+        for (int i : cl.second) {
+            Slot &s = srv->slots[(size_t)i];
+            if (!s.finishing) continue;
+            char *w = srv->arena + s.off;
+            int rc = enqueue_finish(s.r.prob, s.r.cfg, w, s.L, s.r.best_q, s.r.best_pose, cst);
+            if (rc) return rc;
+            SPASM_HIP(hipMemcpyAsync(srv->h_info + 8 * i, w + s.L.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, cst));
+            SPASM_HIP(hipMemcpyAsync(srv->h_finfo + 4 * i, w + s.L.finfo, 4 * sizeof(float), hipMemcpyDeviceToHost,
+                                     cst));
+        }
+        ++li;
     }
-    // 3. finish the solves that reached K
-    for (size_t i = 0; i < srv->slots.size(); ++i) {
-        Slot &s = srv->slots[i];
-        if (!s.used || !s.finishing) continue;
-        char *w = srv->arena + s.off;
-        int rc = enqueue_finish(s.r.prob, s.r.cfg, w, s.L, s.r.best_q, s.r.best_pose, st);
-        if (rc) return rc;
-        SPASM_HIP(hipMemcpyAsync(srv->h_info + 8 * i, w + s.L.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        SPASM_HIP(hipMemcpyAsync(srv->h_finfo + 4 * i, w + s.L.finfo, 4 * sizeof(float), hipMemcpyDeviceToHost, st));
+    SPASM_HIP(hipStreamSynchronize(sa));
+    for (int i = 0; i < N_CLASS_STREAMS; ++i) SPASM_HIP(hipStreamSynchronize(srv->cs[i]));
+    // measured time per iteration of each class (exponentially smoothed)
+    for (const Launch &l : launches) {
+        if (l.event < 0 || l.iters <= 0) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, srv->ev[2 * l.event], srv->ev[2 * l.event + 1]) != hipSuccess) continue;
+        const double per = ms / l.iters;
+        auto it = srv->ms_per_iter.find(l.key);
+        if (it == srv->ms_per_iter.end())
+            srv->ms_per_iter[l.key] = per;
+        else
+            it->second = 0.5 * it->second + 0.5 * per;
     }
-    SPASM_HIP(hipStreamSynchronize(st));
-    // 4. retire
+    // 4. retire; requests admitted in this step are ready from the next one
     int active = 0;
     for (size_t i = 0; i < srv->slots.size(); ++i) {
         Slot &s = srv->slots[i];
         if (!s.used) continue;
         s.steps++;
+        if (!s.ready) {
+            s.ready = true;
+            ++active;
+            continue;
+        }
         s.k_done = s.k_next;
         if (!s.finishing) {
             ++active;
@@ -270,6 +342,8 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         srv->done.push_back(c);
         srv->release(s.off, s.bytes);
         s.used = false;
+        s.ready = false;
+        s.finishing = false;
     }
     if (n_active) *n_active = active;
     if (n_pending) *n_pending = (int32_t)srv->pending.size();

@@ -89,7 +89,8 @@ def test_admission_follows_budget(sp):
     assert active == 1 and pending == 1
     done = _drain(srv)
     assert sorted(done) == [0, 1]
-    assert done[1]["steps"] == 4 and done[0]["steps"] == 4            # 40 iterations / 10 per step
+    # one admission step (prefix), then 40 iterations / 10 per step for a request alone
+    assert done[1]["steps"] == 5 and done[0]["steps"] == 5
     big = _req(sp, 13, 4, 10, 32, 512, 40)
     with pytest.raises(sp.SpasmError):
         srv.submit(*big, 2)
