@@ -173,11 +173,32 @@ int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, floa
  * order.  1 <= M <= N <= 16384.  d_key [N], d_idx [M] int32. */
 int spasm_select_topm(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *stream);
 
+/* The same selection for up to 2^20 keys (M <= 8192 when N > 16384): rounds of 16384-key
+ * workgroup sorts keep each chunk's M smallest keys; keys are unique (cost bits, index),
+ * so the M smallest kept keys are the M smallest of all, in the same order.  d_work:
+ * spasm_select_topm_workspace(N, M) bytes (0 for N <= 16384; d_work may then be NULL). */
+size_t spasm_select_topm_workspace(int32_t N, int32_t M);
+int spasm_select_topm_large(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *d_work,
+                            size_t work_bytes, void *stream);
+
 /* Alg. 1 GetSatisfyingParticles + re-evaluated ArgSort: order of all n particles with the
  * satisfying ones (viol < eps) first, each group by cost then index; d_nsat [1] int32
  * receives the number of satisfying particles.  n <= 16384. */
 int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, int32_t *d_order,
                 int32_t *d_nsat, void *stream);
+
+/* --- placement only (Alg. 1, one round) ---------------------------------------------------
+ * Stage 1 without trajectory optimisation: sample N placements (round `round` of the
+ * sample stream), score them (linear phase), keep the M best (N up to 2^20 as in
+ * spasm_select_topm_large), run the k_lin1 + k_quad1 descent on them, and write them in
+ * satisfying-first order: d_x [M][B][3] (x, y, yaw), d_cost / d_viol [M] (nullable,
+ * quadratic phase), d_nsat [1] the number of satisfying placements.  d_work:
+ * spasm_place_workspace(prob, N, M) bytes, 256-byte aligned.  Callers that want the time
+ * to a first feasible placement repeat rounds until *d_nsat > 0. */
+size_t spasm_place_workspace(spasm_problem prob, int32_t N, int32_t M);
+int spasm_place_round(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, int32_t round, void *d_work,
+                      size_t work_bytes, float *d_x, float *d_cost, float *d_viol, int32_t *d_nsat,
+                      void *stream);
 
 /* --- lift and seeding (Sec. III-B) -----------------------------------------------------
  * Damped least squares IK on the block frame T_E G^-1 (the paper allows any parallel

@@ -1,6 +1,7 @@
 // C-ABI host side of the SPaSM engine: argument validation, problem packing and
 // upload, launch of the device pipeline.  No entry point computes anything on the host.
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -398,6 +399,99 @@ extern "C" int spasm_select_topm(int32_t N, const float *d_key, int32_t M, int32
     int rc = ensure_attrs();
     if (rc) return rc;
     SPASM_HIP(launch_sort_keys(0, N, d_key, nullptr, 0.f, M, d_idx, nullptr, nullptr, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+static int check_topm_shape(int32_t N, int32_t M)
+{
+    if (N < 1 || N > MAX_TOPM_N) return fail(SPASM_EUNSUPPORTED, "N=%d outside 1..%d", N, MAX_TOPM_N);
+    if (M < 1 || M > N) return fail(SPASM_EINVAL, "M=%d outside 1..N", M);
+    if (N > MAX_SORT && M > MAX_TOPM_M)
+        return fail(SPASM_EUNSUPPORTED, "M=%d above %d for N > %d", M, MAX_TOPM_M, MAX_SORT);
+    return SPASM_OK;
+}
+
+extern "C" size_t spasm_select_topm_workspace(int32_t N, int32_t M)
+{
+    if (check_topm_shape(N, M)) return 0;
+    return topm_workspace(N, M);
+}
+
+extern "C" int spasm_select_topm_large(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *d_work,
+                                       size_t work_bytes, void *stream)
+{
+    int rc = check_topm_shape(N, M);
+    if (rc) return rc;
+    if (!d_key || !d_idx) return fail(SPASM_EINVAL, "NULL buffer");
+    const size_t need = topm_workspace(N, M);
+    if (work_bytes < need || (need && !d_work))
+        return fail(SPASM_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    rc = ensure_attrs();
+    if (rc) return rc;
+    SPASM_HIP(launch_topm(N, d_key, M, d_idx, d_work, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
+namespace {
+struct PlaceLayout {
+    size_t x1, c1, v1, idx, xs, cs, vs, ord, topm, total;
+};
+PlaceLayout place_layout(int B, int N, int M)
+{
+    PlaceLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.x1 = take((size_t)N * B * 3 * sizeof(float));
+    L.c1 = take((size_t)N * sizeof(float));
+    L.v1 = take((size_t)N * sizeof(float));
+    L.idx = take((size_t)M * sizeof(int32_t));
+    L.xs = take((size_t)M * B * 3 * sizeof(float));
+    L.cs = take((size_t)M * sizeof(float));
+    L.vs = take((size_t)M * sizeof(float));
+    L.ord = take((size_t)M * sizeof(int32_t));
+    L.topm = take(topm_workspace(N, M));
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+extern "C" size_t spasm_place_workspace(spasm_problem prob, int32_t N, int32_t M)
+{
+    if (!prob || check_topm_shape(N, M)) return 0;
+    return place_layout(prob->kp.B, N, M).total;
+}
+
+extern "C" int spasm_place_round(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, int32_t round, void *d_work,
+                                 size_t work_bytes, float *d_x, float *d_cost, float *d_viol, int32_t *d_nsat,
+                                 void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    int rc = check_topm_shape(N, M);
+    if (rc) return rc;
+    if (round < 0) return fail(SPASM_EINVAL, "round=%d must be >= 0", round);
+    if (!d_x || !d_nsat) return fail(SPASM_EINVAL, "NULL output buffer");
+    const PlaceLayout L = place_layout(prob->kp.B, N, M);
+    if (!d_work || work_bytes < L.total) return fail(SPASM_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, L.total);
+    if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace is not 256-byte aligned");
+    rc = ensure_attrs();
+    if (rc) return rc;
+    const KProb &K = prob->kp;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)d_work;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    SPASM_HIP(launch_sample(K, N, seed, round, F(L.x1), nullptr, st));
+    SPASM_HIP(launch_place(K, N, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1), nullptr, nullptr,
+                           st));
+    SPASM_HIP(launch_topm(N, F(L.c1), M, I(L.idx), w + L.topm, st));
+    SPASM_HIP(launch_place(K, M, F(L.x1), I(L.idx), F(L.xs), 1, prob->k_total1 + 1, SPASM_PHASE_QUAD, F(L.cs), F(L.vs),
+                           nullptr, nullptr, st));
+    SPASM_HIP(launch_sort_keys(1, M, F(L.cs), F(L.vs), prob->sat_eps, M, I(L.ord), d_nsat, nullptr, st));
+    SPASM_HIP(launch_gather_place(K.B, M, F(L.xs), F(L.cs), F(L.vs), I(L.ord), d_x, d_cost, d_viol, st));
     return SPASM_OK;
 }
 

@@ -10,6 +10,8 @@
 //             l adds z_{j-1} . ((c - o_{j-1}) x f) to dC/dq_j for every j <= l.
 //   optimise  the whole schedule runs inside one launch with the state on chip
 //             (trajectory in VGPRs, Adam moments and poses in LDS).
+#include <algorithm>
+
 #include "spasm_internal.h"
 
 namespace spasm {
@@ -1203,6 +1205,64 @@ __global__ __launch_bounds__(1024) void k_sort(int kind, int n, const float *cos
     if (tid == 0 && out_count) *out_count = kind == 0 ? M : s_cnt;
 }
 
+// Chunked top-M for more keys than one workgroup sorts: workgroup g sorts the keys of
+// its chunk [g chunk, min(n, (g + 1) chunk)) -- built from cost and index in the first
+// round, read from in_keys later -- and keeps its min(M, len) smallest, to out_keys at
+// g M (rounds before the last) or as indices to out_idx (last round, one workgroup).
+// Keys are unique (cost bits, index), so the M smallest kept keys are the M smallest of
+// all, in the same order as one sort of everything.
+__global__ __launch_bounds__(1024) void k_topm_round(int n, const float *cost, const unsigned long long *in_keys,
+                                                     int chunk, int M, unsigned long long *out_keys, int32_t *out_idx)
+{
+    extern __shared__ unsigned long long s_keys[];
+    const int tid = threadIdx.x, lo = blockIdx.x * chunk, len = min(chunk, n - lo);
+    int npow = 1;
+    while (npow < len) npow <<= 1;
+    for (int i = tid; i < npow; i += blockDim.x) {
+        unsigned long long key = ~0ull;
+        if (i < len)
+            key = in_keys ? in_keys[lo + i]
+                          : ((unsigned long long)ordered_bits(cost[lo + i]) << 32) | (unsigned)(lo + i);
+        s_keys[i] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= npow; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < npow; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long x = s_keys[i], y = s_keys[ixj];
+                    if ((x > y) == ((i & k) == 0)) {
+                        s_keys[i] = y;
+                        s_keys[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int m = min(M, len);
+    for (int i = tid; i < m; i += blockDim.x) {
+        if (out_idx)
+            out_idx[i] = (int32_t)(s_keys[i] & 0xffffffffu);
+        else
+            out_keys[(size_t)blockIdx.x * M + i] = s_keys[i];
+    }
+}
+
+// Placement round output: particles in satisfying-first order with their cost and
+// violation.
+__global__ void k_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,
+                               float *x_out, float *c_out, float *v_out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int src = ord[i];
+    for (int k = 0; k < 3 * B; ++k) x_out[(size_t)i * 3 * B + k] = xs[(size_t)src * 3 * B + k];
+    if (c_out) c_out[i] = cs[src];
+    if (v_out) v_out[i] = vs[src];
+}
+
 // ------------------------------------------------------------------------------------
 // Lift (damped least squares on the block frame) and trajectory seeding.
 // ------------------------------------------------------------------------------------
@@ -1619,6 +1679,8 @@ hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_topm_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
+    if (e != hipSuccess) return e;
 #define SPASM_TRAJ_ATTR(CH)                                                                                      \
     e = hipFuncSetAttribute((const void *)k_traj<2, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
     if (e != hipSuccess) return e;                                                                           \
@@ -1639,6 +1701,43 @@ hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *vio
     while (npow < n) npow <<= 1;
     const size_t shm = (size_t)npow * sizeof(unsigned long long);
     hipLaunchKernelGGL(k_sort, dim3(1), dim3(1024), shm, st, kind, n, cost, viol, eps, M, out_idx, out_count, skip);
+    return hipGetLastError();
+}
+
+size_t topm_workspace(int n, int M)
+{
+    if (n <= MAX_SORT) return 0;
+    return 2 * (size_t)((n + MAX_SORT - 1) / MAX_SORT) * (size_t)M * sizeof(unsigned long long);
+}
+
+hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *ws, hipStream_t st)
+{
+    if (n <= MAX_SORT) return launch_sort_keys(0, n, cost, nullptr, 0.f, M, out_idx, nullptr, nullptr, st);
+    unsigned long long *buf[2] = {(unsigned long long *)ws,
+                                  (unsigned long long *)ws + (size_t)((n + MAX_SORT - 1) / MAX_SORT) * M};
+    const unsigned long long *in = nullptr;
+    int count = n, r = 0;
+    const size_t shm_full = (size_t)MAX_SORT * sizeof(unsigned long long);
+    while (count > MAX_SORT) {  // M < MAX_SORT: every round shrinks count
+        const int G = (count + MAX_SORT - 1) / MAX_SORT;
+        hipLaunchKernelGGL(k_topm_round, dim3(G), dim3(1024), shm_full, st, count, in ? nullptr : cost, in, MAX_SORT,
+                           M, buf[r & 1], (int32_t *)nullptr);
+        count = (G - 1) * M + std::min(M, count - (G - 1) * MAX_SORT);
+        in = buf[r & 1];
+        ++r;
+    }
+    int npow = 1;
+    while (npow < count) npow <<= 1;
+    hipLaunchKernelGGL(k_topm_round, dim3(1), dim3(1024), (size_t)npow * sizeof(unsigned long long), st, count,
+                       (const float *)nullptr, in, count, M, (unsigned long long *)nullptr, out_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,
+                               float *x_out, float *c_out, float *v_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_place, dim3((M + 255) / 256), dim3(256), 0, st, B, M, xs, cs, vs, ord, x_out, c_out,
+                       v_out);
     return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ constexpr int NJ = 7;           // joints of the serial chain
 constexpr int MAX_B = 16;       // blocks per problem
 constexpr int MAX_THREADS = 1024;
 constexpr int MAX_SORT = 16384; // single-workgroup sort capacity (LDS bound)
+constexpr int MAX_TOPM_N = 1 << 20;  // chunked top-M: keys
+constexpr int MAX_TOPM_M = MAX_SORT / 2;  // chunked top-M: kept per chunk (each round halves at least)
 
 // Problem constants passed BY VALUE to every kernel: they land in the kernel-argument
 // segment and are read into scalar registers, so every lane of a wave shares one copy.
@@ -84,6 +86,10 @@ hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes);
 hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *viol, float eps,
                             int M, int32_t *out_idx, int32_t *out_count, const int *skip,
                             hipStream_t st);
+size_t topm_workspace(int n, int M);
+hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *ws, hipStream_t st);
+hipError_t launch_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,
+                               float *x_out, float *c_out, float *v_out, hipStream_t st);
 
 hipError_t launch_ik_iterate(const KProb &P, int kind, int n, const float *target, float *q,
                              int iters, hipStream_t st);

@@ -64,6 +64,11 @@ SYMBOLS = {
     "spasm_optimize": ([c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp], c_i32),
     "spasm_select_topm": ([c_i32, c_vp, c_i32, c_vp, c_vp], c_i32),
     "spasm_order": ([c_i32, c_vp, c_vp, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
+    "spasm_select_topm_workspace": ([c_i32, c_i32], ctypes.c_size_t),
+    "spasm_select_topm_large": ([c_i32, c_vp, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp], c_i32),
+    "spasm_place_workspace": ([c_vp, c_i32, c_i32], ctypes.c_size_t),
+    "spasm_place_round": ([c_vp, c_i32, c_i32, c_u64, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp, c_vp],
+                          c_i32),
     "spasm_ik_iterate": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp], c_i32),
     "spasm_ik_lift": ([c_vp, c_i32, c_vp, c_u64, c_i32, c_vp, c_vp, c_vp], c_i32),
     "spasm_traj_init": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_u64, c_vp, c_vp], c_i32),
@@ -207,6 +212,22 @@ class Problem:
         _check(load().spasm_optimize(self.handle, STAGE_PLACE, N, 0, _dev(x, (N, self.B, 3), name="x"), None, None,
                                      k_begin, k_end, 0, _dev(cost), _dev(viol), _stream()))
         return cost, viol
+
+    def place_workspace(self, N, M):
+        n = load().spasm_place_workspace(self.handle, N, M)
+        if n == 0:
+            raise SpasmError(f"unsupported placement round shape N={N} M={M}")
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def place_round(self, N, M, seed, rnd=0, work=None):
+        """One placement-only round: returns (x [M, B, 3] satisfying first, cost [M], viol [M],
+        nsat [1] int32), all on the device."""
+        work = self.place_workspace(N, M) if work is None else work
+        x, cost, viol = _empty(M, self.B, 3), _empty(M), _empty(M)
+        nsat = _empty(1, dtype=torch.int32)
+        _check(load().spasm_place_round(self.handle, N, M, seed, rnd, _dev(work, dtype=torch.uint8), work.numel(),
+                                        _dev(x), _dev(cost), _dev(viol), _dev(nsat, dtype=torch.int32), _stream()))
+        return x, cost, viol, nsat
 
     # ---- stage 2 ----------------------------------------------------------------------
     def traj_cost(self, q, pose, phase=PHASE_LIN, grad=True):
@@ -352,6 +373,19 @@ def select_topm(key, M):
     N = key.shape[0]
     idx = _empty(M, dtype=torch.int32)
     _check(load().spasm_select_topm(N, _dev(key, (N,), name="key"), M, _dev(idx, dtype=torch.int32), _stream()))
+    return idx
+
+
+def select_topm_large(key, M, work=None):
+    """select_topm for up to 2^20 keys (chunked rounds); allocates its workspace if not given."""
+    N = key.shape[0]
+    need = load().spasm_select_topm_workspace(N, M)
+    if work is None and need:
+        work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    idx = _empty(M, dtype=torch.int32)
+    _check(load().spasm_select_topm_large(N, _dev(key, (N,), name="key"), M, _dev(idx, dtype=torch.int32),
+                                          _dev(work, dtype=torch.uint8) if need else None,
+                                          work.numel() if need else 0, _stream()))
     return idx
 
 

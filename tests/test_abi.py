@@ -131,3 +131,19 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(spasm, "_lib", None)
     with pytest.raises(spasm.SpasmError):
         spasm.load()
+
+
+def test_topm_and_place_shapes():
+    """Chunked selection and placement-round shape checks run on the host."""
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    assert L.spasm_select_topm_workspace(16384, 2048) == 0
+    assert L.spasm_select_topm_workspace(131072, 256) == 2 * 8 * 256 * 8
+    assert L.spasm_select_topm_workspace(1 << 21, 256) == 0          # too many keys
+    assert L.spasm_select_topm_workspace(20000, 8193) == 0           # M too large for chunking
+    dummy = ctypes.c_void_p(256)
+    assert L.spasm_select_topm_large(1 << 21, dummy, 8, dummy, None, 0, None) == -4
+    assert L.spasm_select_topm_large(20000, dummy, 8193, dummy, None, 0, None) == -4
+    assert L.spasm_select_topm_large(20000, dummy, 0, dummy, None, 0, None) == -1
+    assert L.spasm_select_topm_large(20000, dummy, 8, dummy, None, 0, None) == -1   # no workspace
+    assert L.spasm_place_round(None, 100, 10, 0, 0, None, 0, dummy, None, None, dummy, None) == -1

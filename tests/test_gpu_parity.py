@@ -257,6 +257,38 @@ def test_topm_bit_exact(sp, orc):
         assert np.array_equal(idx, ref), (n, m)
 
 
+def test_topm_large_bit_exact(sp, orc):
+    """Chunked top-M beyond one workgroup: ragged tails, ties across chunk borders, and
+    the most rounds (M = 8192 halves the candidates per round)."""
+    rng = np.random.default_rng(702)
+    for n, m in [(16385, 8192), (131072 + 123, 256), (1 << 20, 8192), (40000, 1)]:
+        key = np.round(rng.uniform(0, 1, n), 4).astype(np.float32)  # many ties
+        idx = N(sp.select_topm_large(T(key), m)).astype(np.int64)
+        ref = np.argsort(key.astype(np.float64), kind="stable")[:m]
+        assert np.array_equal(idx, ref), (n, m)
+    # at or below one workgroup it is the plain selection
+    key = np.round(rng.uniform(0, 1, 5000), 3).astype(np.float32)
+    assert torch.equal(sp.select_topm_large(T(key), 700), sp.select_topm(T(key), 700))
+
+
+def test_place_round_equals_pieces(sp):
+    """One placement-only round equals sample -> linear score -> top-M -> descent -> order
+    run through the separate entry points (each parity-tested against the oracle)."""
+    prob, pr, _ = synth.config("tower4", 0)
+    dev = sp.Problem(prob, pr)
+    for N_, M_, rnd in [(2048, 256, 0), (40000, 512, 3)]:
+        x, cost, viol, nsat = dev.place_round(N_, M_, seed=9, rnd=rnd)
+        xs = dev.sample(N_, 9, rnd)
+        c1, _, _ = dev.place_cost(xs, phase=sp.PHASE_LIN, grad=False)
+        idx = sp.select_topm_large(c1, M_).long()
+        xm = xs[idx].contiguous()
+        cq, vq = dev.place_optimize(xm, 1, pr.k_lin1 + pr.k_quad1 + 1)
+        ordr, ns = sp.order(cq, vq, pr.sat_eps)
+        ordr = ordr.long()
+        assert int(N(ns)[0]) == int(N(nsat)[0])
+        assert torch.equal(x, xm[ordr]) and torch.equal(cost, cq[ordr]) and torch.equal(viol, vq[ordr])
+
+
 def test_order_bit_exact(sp, orc):
     rng = np.random.default_rng(701)
     prob, pr, _ = synth.config("tower4", 0)
