@@ -210,9 +210,11 @@ int spasm_place_round(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, i
  *   block_init[b]: start 0 at q_home + ik_noise U[-1,1]^7 (counter (particle, 2b + chunk,
  *   0, 2)), start r >= 1 uniform over the limits (counter (particle, 2b + chunk, r, 2)).
  *   Place at d_pose[p][b]: start 0 from the chosen grasp solution, start r >= 1 uniform
- *   (counter (particle, 2B + 2b + chunk, r, 2)).  Each solve keeps the first start whose
- *   final error |e| (position and orientation error of the iteration) is below 1e-4,
- *   otherwise the start with the smallest error (the first on ties).
+ *   (counter (particle, 2B + 2b + chunk, r, 2)).  Among the starts whose final error |e|
+ *   (position and orientation error of the iteration) is below 1e-4 each solve keeps the
+ *   one with the smallest arm-obstacle penetration (sum over robot spheres and boxes of
+ *   max(0, r - sdf); the first on ties); when none converged, the start with the smallest
+ *   error (the first on ties).
  *   d_qgrasp, d_qplace [P][B][7]. */
 int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d_target, float *d_q,
                      int32_t iters, void *stream);

@@ -73,6 +73,8 @@ def lib():
         L.or_ik_lift.argtypes = [P, i, vp, u64, i, d, d, i, vp, vp]
         L.or_ik_error.argtypes = [P, i, vp, vp]
         L.or_ik_error.restype = d
+        L.or_arm_obstacle_pen.argtypes = [P, vp]
+        L.or_arm_obstacle_pen.restype = d
         L.or_traj_init.argtypes = [P, i, i, vp, vp, u64, d, vp]
         L.or_stage1.argtypes = [P, i, i, u64, i, i, i, d, d, vp, vp, vp]
         L.or_stage2.argtypes = [P, i, i, i, i, d, d, d, d, d, vp, vp]
@@ -188,6 +190,10 @@ class Oracle:
     def ik_error(self, kind, target, q):
         """|e| of the IK iteration at q (position and orientation error of the block frame)."""
         return lib().or_ik_error(self.ref, kind, _ptr(_f64(target)), _ptr(_f64(q)))
+
+    def arm_obstacle_pen(self, q):
+        """Sum over robot spheres and boxes of max(0, r - sdf) at the configuration q."""
+        return lib().or_arm_obstacle_pen(self.ref, _ptr(_f64(q)))
 
     def ik_lift(self, pose, seed, iters=None):
         pose = _f64(pose)

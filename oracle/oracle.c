@@ -858,15 +858,35 @@ void or_ik_iterate(const or_problem *pb, int kind, const double *target, double 
     }
 }
 
+/* Sum over the robot spheres and obstacle boxes of max(0, r - sdf) at q: how deep the
+ * arm stands in the clutter. */
+double or_arm_obstacle_pen(const or_problem *pb, const double *q)
+{
+    frame F[9];
+    fk_frames(pb, q, F);
+    double pen = 0.0;
+    for (int i = 0; i < pb->S; ++i) {
+        double c[3], g[3];
+        apply(&F[pb->sph_link[i]], pb->sph_c + 3 * i, c);
+        for (int o = 0; o < pb->O; ++o) {
+            const double d = pb->sph_r[i] - box_sdf_ex(c, pb->boxes + 6 * o, g, NULL);
+            if (d > 0.0) pen += d;
+        }
+    }
+    return pen;
+}
+
 /* One multi-start solve: start 0 is q0, start r >= 1 is uniform over the joint limits
- * (counter (particle, sub, r, stream 2) and (particle, sub + 1, r, stream 2)).  The
- * result is the first start whose final error is below OR_IK_ACCEPT, otherwise the
- * start with the smallest error (the first one on ties). */
+ * (counter (particle, sub, r, stream 2) and (particle, sub + 1, r, stream 2)).  Among
+ * the starts whose final error is below OR_IK_ACCEPT the result is the one standing
+ * least deep in the obstacles (the first on ties); when no start converges, the one with
+ * the smallest error (the first on ties). */
 #define OR_IK_ACCEPT 1e-4
 static void ik_multistart(const or_problem *pb, int kind, const double *target, const double *q0, uint64_t seed,
                           int p, int sub, int restarts, int iters, double lambda, double *q_out)
 {
-    double best = INFINITY;
+    double best_err = INFINITY, best_pen = INFINITY;
+    int have_acc = 0;
     for (int r = 0; r < restarts; ++r) {
         double q[NJ];
         if (r == 0) {
@@ -879,11 +899,17 @@ static void ik_multistart(const or_problem *pb, int kind, const double *target, 
         }
         or_ik_iterate(pb, kind, target, q, iters, lambda);
         const double err = or_ik_error(pb, kind, target, q);
-        if (err < best) {
-            best = err;
+        if (err < OR_IK_ACCEPT) {
+            const double pen = or_arm_obstacle_pen(pb, q);
+            if (!have_acc || pen < best_pen) {
+                have_acc = 1;
+                best_pen = pen;
+                for (int j = 0; j < NJ; ++j) q_out[j] = q[j];
+            }
+        } else if (!have_acc && err < best_err) {
+            best_err = err;
             for (int j = 0; j < NJ; ++j) q_out[j] = q[j];
         }
-        if (err < OR_IK_ACCEPT) break;
     }
 }
 

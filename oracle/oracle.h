@@ -57,6 +57,7 @@ void or_order(int n, const double *cost, const double *viol, double eps, int32_t
 void or_ik_iterate(const or_problem *pb, int kind, const double *target, double *q,
                    int iters, double lambda);
 double or_ik_error(const or_problem *pb, int kind, const double *target, const double *q);
+double or_arm_obstacle_pen(const or_problem *pb, const double *q);
 void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, int iters,
                 double lambda, double noise, int restarts, double *q_grasp, double *q_place);
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp,

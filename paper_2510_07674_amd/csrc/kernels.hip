@@ -1416,15 +1416,48 @@ __global__ void k_ik_iterate(KProb P, int kind, int n, const float *target, floa
     for (int j = 0; j < NJ; ++j) qio[(size_t)gid * NJ + j] = q[j];
 }
 
+// Sum over the robot spheres and obstacle boxes of max(0, r - sdf) at q (dense: it runs
+// once per IK start).  Padded spheres (r = -1e30) contribute nothing.
+__device__ __forceinline__ float arm_obstacle_pen(const KProb &P, const float (&q)[NJ])
+{
+    Frame F;
+    frame_identity(F);
+    float pen = 0.f;
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
+        for (int s = P.link_start[J]; s < P.link_start[J + 1]; ++s) {
+            const float4 sp = ldc(P.sph, s);
+            const float cx = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
+            const float cy = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
+            const float cz = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
+            for (int o = 0; o < P.O; ++o) {
+                const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
+                const float ux = fabsf(cx - bc.x) - be.x, uy = fabsf(cy - bc.y) - be.y, uz = fabsf(cz - bc.z) - be.z;
+                const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
+                const float sdf = __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz) + fminf(fmaxf(fmaxf(ux, uy), uz), 0.f);
+                pen += fmaxf(sp.w - sdf, 0.f);
+            }
+        }
+    }
+    return pen;
+}
+
 // Multi-start lift: eight lanes per (particle, block), lane r runs start r < restarts
 // (start 0 from q_home + noise, resp. from the chosen grasp; the others uniform over the
-// limits).  The group keeps the first start whose error is below 1e-4, otherwise the
-// smallest error (first on ties), and broadcasts it to the group.
-__device__ __forceinline__ int ik_pick(float err, int r, int restarts)
+// limits).  Among the starts whose error is below 1e-4 the group keeps the one standing
+// least deep in the obstacles (first on ties); when none converged, the smallest error
+// (first on ties).  The choice is broadcast to the group.
+__device__ __forceinline__ int ik_pick(float err, float pen, int r, int restarts)
 {
     const int lane = threadIdx.x & 63, g0 = lane & ~7;
-    const unsigned long long acc = (__ballot(r < restarts && err < 1e-4f) >> g0) & 0xFFull;
-    if (acc) return g0 + __builtin_ctzll(acc);
+    const bool ok = r < restarts && err < 1e-4f;
+    const unsigned long long acc = (__ballot(ok) >> g0) & 0xFFull;
+    if (acc) {
+        const float sc = ok ? pen : INFINITY;
+        const float m = group8_reduce(sc, OpMin());
+        return g0 + __builtin_ctzll((__ballot(ok && sc == m) >> g0) & 0xFFull);
+    }
     const float e = r < restarts ? err : INFINITY;
     const float m = group8_reduce(e, OpMin());
     const unsigned long long at = (__ballot(e == m) >> g0) & 0xFFull;
@@ -1446,12 +1479,13 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
         q[j] = r == 0 ? fminf(fmaxf(P.q_home[j] + P.ik_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j])
                       : P.lo[j] + (P.hi[j] - P.lo[j]) * u[j];
     const float4 I = ldc(P.blk_init, 2 * b);
-    float err = INFINITY;
+    float err = INFINITY, pen = 0.f;
     if (r < R) {
         ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
         err = ik_error(P, 0, I.x, I.y, I.z, 0.f, q);
+        if (err < 1e-4f) pen = arm_obstacle_pen(P, q);
     }
-    int src = ik_pick(err, r, R);
+    int src = ik_pick(err, pen, r, R);
     float qc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qc[j] = __shfl(q[j], src, 64);
@@ -1465,11 +1499,13 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     for (int j = 0; j < NJ; ++j) q[j] = r == 0 ? qc[j] : P.lo[j] + (P.hi[j] - P.lo[j]) * u[j];
     const float *t = pose + (size_t)grp * 4;
     err = INFINITY;
+    pen = 0.f;
     if (r < R) {
         ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
         err = ik_error(P, 1, t[0], t[1], t[2], t[3], q);
+        if (err < 1e-4f) pen = arm_obstacle_pen(P, q);
     }
-    src = ik_pick(err, r, R);
+    src = ik_pick(err, pen, r, R);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qc[j] = __shfl(q[j], src, 64);
     if (r == 0) {

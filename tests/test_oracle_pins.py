@@ -700,10 +700,34 @@ def test_traj_init_closed_form(orc):
             assert np.all(np.abs(q[p, s, m] - 0.5 * (qa + end)) <= pr.mid_noise + 1e-12)
 
 
+def _np_arm_pen(o, prob, q):
+    """Sum of max(0, r - sdf) over robot spheres and boxes, box SDF written out in numpy."""
+    F = o.fk(q).reshape(9, 12)
+    R, t = F[:, :9].reshape(9, 3, 3), F[:, 9:]
+    c = np.einsum("sij,sj->si", R[prob.sph_link], prob.sph_c) + t[prob.sph_link]
+    u = np.abs(c[:, None, :] - prob.boxes[None, :, :3]) - prob.boxes[None, :, 3:]
+    sdf = np.linalg.norm(np.maximum(u, 0.0), axis=-1) + np.minimum(u.max(-1), 0.0)
+    return float(np.maximum(prob.sph_r[:, None] - sdf, 0.0).sum())
+
+
+def test_arm_obstacle_pen_matches_numpy(orc):
+    prob, pr, _ = synth.config("tower4", 0)
+    o = orc.Oracle(prob, pr)
+    rng = np.random.default_rng(31)
+    deep = 0
+    for _ in range(40):
+        q = rng.uniform(prob.lo, prob.hi)
+        ref = _np_arm_pen(o, prob, q)
+        assert o.arm_obstacle_pen(q) == pytest.approx(ref, rel=1e-12, abs=1e-14)
+        deep += ref > 0.0
+    assert deep > 5   # the draw does reach into the clutter
+
+
 def test_ik_lift_multistart_rule(orc):
     """Multi-start lift, rebuilt by brute force: starts from numpy's Philox (counter
     (particle, sub, start, 2), 24-bit uniforms), one IK solve per start, and the rule
-    'first start with error < 1e-4, else the smallest error (first on ties)'."""
+    'among starts with error < 1e-4 the least arm-obstacle penetration (first on ties),
+    else the smallest error (first on ties)', penetration from a numpy box SDF."""
     prob, pr, _ = synth.config("tower4", 3)
     o = orc.Oracle(prob, pr)
     rng = np.random.default_rng(23)
@@ -720,28 +744,26 @@ def test_ik_lift_multistart_rule(orc):
         return np.array(u[:7])
 
     def pick(kind, target, starts):
-        best, qb = np.inf, None
-        for q0 in starts:
-            q = o.ik_iterate(kind, target, q0, pr.ik_iters)
-            e = o.ik_error(kind, target, q)
-            if e < best:
-                best, qb = e, q
-            if e < 1e-4:
-                break
-        return qb, best
+        sols = [o.ik_iterate(kind, target, q0, pr.ik_iters) for q0 in starts]
+        errs = [o.ik_error(kind, target, q) for q in sols]
+        acc = [i for i, e in enumerate(errs) if e < 1e-4]
+        if acc:
+            pens = [_np_arm_pen(o, prob, sols[i]) for i in acc]
+            return sols[acc[int(np.argmin(pens))]], True
+        return sols[int(np.argmin(errs))], False
 
-    n_acc = 0
+    n_acc = n_multi = 0
     for p in range(1, P):
         for b in range(B):
             s0 = np.clip(prob.q_home + pr.ik_noise * (2 * u7(p, 2 * b, 0) - 1), prob.lo, prob.hi)
             starts = [s0] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * b, r) for r in range(1, pr.ik_restarts)]
-            g, eg = pick(0, prob.block_init[b], starts)
+            g, ok_g = pick(0, prob.block_init[b], starts)
             assert np.array_equal(g, qg[p, b])
             starts = [g] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * B + 2 * b, r)
                             for r in range(1, pr.ik_restarts)]
-            pl, ep = pick(1, pose[p, b], starts)
+            pl, ok_p = pick(1, pose[p, b], starts)
             assert np.array_equal(pl, qp[p, b])
-            n_acc += (eg < 1e-4) + (ep < 1e-4)
+            n_acc += ok_g + ok_p
     assert n_acc > 0
 
 
