@@ -87,6 +87,7 @@ typedef struct {
     double lin_frac2, eta2, alpha2, beta1, beta2, adam_eps;
     int32_t ik_iters;
     int32_t ik_restarts;  /* IK starts per (particle, block) in the lift, 1..8 */
+    int32_t mid_candidates;  /* intermediate-waypoint draws per segment in the seeding, 1..8 */
     double ik_lambda, ik_noise, mid_noise;
     double sat_eps;   /* a particle satisfies the constraints when its violation < sat_eps */
     int32_t retries;  /* stage-1 resampling rounds when nothing satisfies */
@@ -221,9 +222,12 @@ int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d
 int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose, uint64_t seed, int32_t iters,
                   float *d_qgrasp, float *d_qplace, void *stream);
 
-/* Straight-line seeds through one intermediate waypoint per segment: the midpoint of the
- * segment's ends plus mid_noise U[-1,1]^7 (counter (particle, 2s + chunk, 0, 3)), at
- * index (W-1)/2; the first segment starts at q_home.  d_q [P][2B][W][7]. */
+/* Straight-line seeds through one intermediate waypoint per segment, at index (W-1)/2;
+ * the first segment starts at q_home.  The intermediate waypoint is the best of
+ * mid_candidates draws c of the segment ends' midpoint plus mid_noise U[-1,1]^7 (counter
+ * (particle, 2s + chunk, c, 3)), clamped to the limits: the draw whose seed path has the
+ * smallest arm-obstacle penetration sum at the intermediate waypoint and at the two
+ * points halfway to the ends (the first on ties).  d_q [P][2B][W][7]. */
 int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgrasp,
                     const float *d_qplace, uint64_t seed, float *d_q, void *stream);
 

@@ -75,7 +75,7 @@ def lib():
         L.or_ik_error.restype = d
         L.or_arm_obstacle_pen.argtypes = [P, vp]
         L.or_arm_obstacle_pen.restype = d
-        L.or_traj_init.argtypes = [P, i, i, vp, vp, u64, d, vp]
+        L.or_traj_init.argtypes = [P, i, i, vp, vp, u64, d, i, vp]
         L.or_stage1.argtypes = [P, i, i, u64, i, i, i, d, d, vp, vp, vp]
         L.or_stage2.argtypes = [P, i, i, i, i, d, d, d, d, d, vp, vp]
         _lib = L
@@ -208,7 +208,8 @@ class Oracle:
         qg, qp = _f64(qg), _f64(qp)
         P, B = qg.shape[:2]
         q = np.zeros((P, 2 * B, W, 7))
-        lib().or_traj_init(self.ref, P, W, _ptr(qg), _ptr(qp), seed, self.params.mid_noise, _ptr(q))
+        lib().or_traj_init(self.ref, P, W, _ptr(qg), _ptr(qp), seed, self.params.mid_noise,
+                           self.params.mid_candidates, _ptr(q))
         return q
 
     # -- drivers ---------------------------------------------------------------------------

@@ -937,13 +937,13 @@ void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, 
         }
 }
 
-/* Trajectory seeds (Sec. III-B): one intermediate waypoint sampled between each
- * segment's start and goal, their midpoint plus uniform noise (counter (particle,
- * 2s + chunk, 0, stream 3)), at index m = (W-1)/2, and straight lines start ->
- * intermediate -> goal.  The first segment starts at q_home.  Segment ends are copied
- * exactly so that the shared boundary configurations are equal. */
+/* Trajectory seeds (Sec. III-B): one intermediate waypoint between each segment's start
+ * and goal, at index m = (W-1)/2, and straight lines start -> intermediate -> goal.  The
+ * intermediate waypoint is the best of `candidates` draws of the endpoints' midpoint plus
+ * uniform noise (see below).  The first segment starts at q_home.  Segment ends are
+ * copied exactly so that the shared boundary configurations are equal. */
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, const double *q_place,
-                  uint64_t seed, double noise, double *q)
+                  uint64_t seed, double noise, int candidates, double *q)
 {
     const int B = pb->B, NS = 2 * B, m = (W - 1) / 2;
     double qh[NJ];
@@ -959,11 +959,27 @@ void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, con
                 qa = q_grasp + ((size_t)p * B + b) * NJ;
                 qb = q_place + ((size_t)p * B + b) * NJ;
             }
-            double u[8], qm[NJ];
-            uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), 0, STREAM_MID, u);
-            uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), 0, STREAM_MID, u + 4);
-            for (int j = 0; j < NJ; ++j)
-                qm[j] = clampd(0.5 * (qa[j] + qb[j]) + noise * (2.0 * u[j] - 1.0), pb->lo[j], pb->hi[j]);
+            /* candidate c: midpoint + noise from counter (particle, 2s + chunk, c, stream 3);
+             * keep the one whose seed path stands least deep in the obstacles at the
+             * intermediate waypoint and the two quarter points (first on ties) */
+            double qm[NJ], best = INFINITY;
+            for (int c = 0; c < candidates; ++c) {
+                double u[8], qc[NJ], h1[NJ], h2[NJ];
+                uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), (uint64_t)c, STREAM_MID, u);
+                uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), (uint64_t)c, STREAM_MID, u + 4);
+                for (int j = 0; j < NJ; ++j) {
+                    qc[j] = clampd(0.5 * (qa[j] + qb[j]) + noise * (2.0 * u[j] - 1.0), pb->lo[j], pb->hi[j]);
+                    h1[j] = 0.5 * (qa[j] + qc[j]);
+                    h2[j] = 0.5 * (qc[j] + qb[j]);
+                }
+                const double sc = candidates > 1 ? or_arm_obstacle_pen(pb, qc) + or_arm_obstacle_pen(pb, h1) +
+                                                       or_arm_obstacle_pen(pb, h2)
+                                                 : 0.0;
+                if (c == 0 || sc < best) {
+                    best = sc;
+                    for (int j = 0; j < NJ; ++j) qm[j] = qc[j];
+                }
+            }
             for (int w = 0; w < W; ++w) {
                 double *d = q + (((size_t)p * NS + s) * W + w) * NJ;
                 for (int j = 0; j < NJ; ++j) {
@@ -971,7 +987,9 @@ void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, con
                         d[j] = qa[j];
                     else if (w == W - 1)
                         d[j] = qb[j];
-                    else if (w <= m)
+                    else if (w == m)
+                        d[j] = qm[j];
+                    else if (w < m)
                         d[j] = qa[j] + ((double)w / m) * (qm[j] - qa[j]);
                     else
                         d[j] = qm[j] + ((double)(w - m) / (W - 1 - m)) * (qb[j] - qm[j]);

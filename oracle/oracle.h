@@ -61,7 +61,7 @@ double or_arm_obstacle_pen(const or_problem *pb, const double *q);
 void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, int iters,
                 double lambda, double noise, int restarts, double *q_grasp, double *q_place);
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp,
-                  const double *q_place, uint64_t seed, double noise, double *q);
+                  const double *q_place, uint64_t seed, double noise, int candidates, double *q);
 void or_stage1(const or_problem *pb, int N, int M, uint64_t seed, int round, int k_lin,
                int k_quad, double eta, double alpha, double *x_out, double *cost_out,
                double *viol_out);

@@ -124,6 +124,8 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         return fail(SPASM_EINVAL, "negative iteration count");
     if (prm->ik_restarts < 1 || prm->ik_restarts > 8)
         return fail(SPASM_EINVAL, "ik_restarts=%d outside 1..8", prm->ik_restarts);
+    if (prm->mid_candidates < 1 || prm->mid_candidates > 8)
+        return fail(SPASM_EINVAL, "mid_candidates=%d outside 1..8", prm->mid_candidates);
     const double pv[] = {prm->eta1, prm->alpha1, prm->lin_frac2, prm->eta2, prm->alpha2, prm->beta1, prm->beta2,
                          prm->adam_eps, prm->ik_lambda, prm->ik_noise, prm->mid_noise, prm->sat_eps};
     if (!finite_all(pv, sizeof(pv) / sizeof(pv[0]))) return fail(SPASM_EINVAL, "non-finite parameter");
@@ -269,6 +271,7 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.adam_eps = (float)prm->adam_eps;
     K.ik_iters = prm->ik_iters;
     K.ik_restarts = prm->ik_restarts;
+    K.mid_candidates = prm->mid_candidates;
     K.ik_lambda = (float)prm->ik_lambda;
     K.ik_noise = (float)prm->ik_noise;
     K.mid_noise = (float)prm->mid_noise;

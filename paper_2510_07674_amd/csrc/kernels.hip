@@ -1514,14 +1514,11 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     }
 }
 
-__global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q)
+// Segment ends (start, goal) of segment s of particle p.
+__device__ __forceinline__ void segment_ends(const KProb &P, const float *qg, const float *qp, int p, int s,
+                                             float (&qa)[NJ], float (&qb)[NJ])
 {
-    const int B = P.B, NS = 2 * B;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nP * NS * W) return;
-    const int w = gid % W, s = (gid / W) % NS, p = gid / (W * NS);
-    const int b = s >> 1;
-    float qa[NJ], qb[NJ];
+    const int B = P.B, b = s >> 1;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         if (s & 1) {
@@ -1532,20 +1529,68 @@ __global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float
             qb[j] = qg[((size_t)p * B + b) * NJ + j];
         }
     }
-    float u[8];
-    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), 0, 3u, u);
-    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), 0, 3u, u + 4);
+}
+
+// Intermediate waypoint of each segment: eight lanes per (particle, segment), lane c <
+// mid_candidates draws the ends' midpoint + noise (counter (p, 2s + chunk, c, 3)) and
+// scores the seed path by arm-obstacle penetration at the draw and at the two points
+// halfway to the ends; the lowest score (first on ties) is written to waypoint (W-1)/2.
+__global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const float *qg, const float *qp,
+                                                  uint64_t seed, float *q)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int grp = gid >> 3, c = gid & 7, NS = 2 * P.B, C = P.mid_candidates;
+    if (grp >= nP * NS) return;  // whole 8-lane groups only
+    const int p = grp / NS, s = grp % NS;
+    float qa[NJ], qb[NJ], qc[NJ], h1[NJ], h2[NJ], u[8];
+    segment_ends(P, qg, qp, p, s, qa, qb);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), (uint64_t)c, 3u, u);
+    uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), (uint64_t)c, 3u, u + 4);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        qc[j] = fminf(fmaxf(0.5f * (qa[j] + qb[j]) + P.mid_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
+        h1[j] = 0.5f * (qa[j] + qc[j]);
+        h2[j] = 0.5f * (qc[j] + qb[j]);
+    }
+    float sc = INFINITY;
+    if (c < C) sc = C > 1 ? arm_obstacle_pen(P, qc) + arm_obstacle_pen(P, h1) + arm_obstacle_pen(P, h2) : 0.f;
+    const int lane = threadIdx.x & 63, g0 = lane & ~7;
+    const float best = group8_reduce(sc, OpMin());
+    const int src = g0 + __builtin_ctzll((__ballot(c < C && sc == best) >> g0) & 0xFFull);
+    float qm[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qm[j] = __shfl(qc[j], src, 64);
+    if (c == 0) {
+        float *o = q + (((size_t)p * NS + s) * W + (W - 1) / 2) * NJ;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) o[j] = qm[j];
+    }
+}
+
+// Straight lines start -> intermediate (read from waypoint (W-1)/2, left as it is) -> goal.
+__global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q)
+{
+    const int B = P.B, NS = 2 * B;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nP * NS * W) return;
+    const int w = gid % W, s = (gid / W) % NS, p = gid / (W * NS);
     const int m = (W - 1) / 2;
+    if (w == m) return;  // the chosen intermediate waypoint
+    (void)B;
+    (void)seed;
+    float qa[NJ], qb[NJ];
+    segment_ends(P, qg, qp, p, s, qa, qb);
+    const float *mid = q + (((size_t)p * NS + s) * W + m) * NJ;
     float *o = q + (size_t)gid * NJ;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const float qm = fminf(fmaxf(0.5f * (qa[j] + qb[j]) + P.mid_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
+        const float qm = mid[j];
         float v;
         if (w == 0)
             v = qa[j];
         else if (w == W - 1)
             v = qb[j];
-        else if (w <= m)
+        else if (w < m)
             v = qa[j] + ((float)w / (float)m) * (qm - qa[j]);
         else
             v = qm + ((float)(w - m) / (float)(W - 1 - m)) * (qb[j] - qm);
@@ -1794,6 +1839,8 @@ hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t se
 hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q,
                             hipStream_t st)
 {
+    const long g = (long)nP * 2 * P.B * 8;
+    hipLaunchKernelGGL(k_seed_mid, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, P, nP, W, qg, qp, seed, q);
     const int n = nP * 2 * P.B * W;
     hipLaunchKernelGGL(k_traj_init, dim3((n + 255) / 256), dim3(256), 0, st, P, nP, W, qg, qp, seed, q);
     return hipGetLastError();

@@ -36,7 +36,7 @@ struct KProb {
     int k_lin1, k_quad1;
     float eta1, alpha1;
     float eta2, alpha2, beta1, beta2, adam_eps;
-    int ik_iters, ik_restarts;
+    int ik_iters, ik_restarts, mid_candidates;
     float ik_lambda, ik_noise, mid_noise, sat_eps;
 };
 

@@ -34,7 +34,7 @@ class SkeletonDesc(ctypes.Structure):
 class ParamsDesc(ctypes.Structure):
     _fields_ = [("w", c_d * 9), ("k_lin1", c_i32), ("k_quad1", c_i32), ("eta1", c_d), ("alpha1", c_d),
                 ("lin_frac2", c_d), ("eta2", c_d), ("alpha2", c_d), ("beta1", c_d), ("beta2", c_d),
-                ("adam_eps", c_d), ("ik_iters", c_i32), ("ik_restarts", c_i32), ("ik_lambda", c_d), ("ik_noise", c_d),
+                ("adam_eps", c_d), ("ik_iters", c_i32), ("ik_restarts", c_i32), ("mid_candidates", c_i32), ("ik_lambda", c_d), ("ik_noise", c_d),
                 ("mid_noise", c_d), ("sat_eps", c_d), ("retries", c_i32)]
 
 
@@ -142,7 +142,7 @@ def chain_desc(prob) -> ChainDesc:
 def params_desc(pr) -> ParamsDesc:
     p = ParamsDesc()
     p.w[:] = [float(v) for v in pr.weights()]
-    for name in ("k_lin1", "k_quad1", "ik_iters", "ik_restarts", "retries"):
+    for name in ("k_lin1", "k_quad1", "ik_iters", "ik_restarts", "mid_candidates", "retries"):
         setattr(p, name, int(getattr(pr, name)))
     for name in ("eta1", "alpha1", "lin_frac2", "eta2", "alpha2", "beta1", "beta2", "adam_eps", "ik_lambda",
                  "ik_noise", "mid_noise", "sat_eps"):

@@ -107,6 +107,7 @@ class Params:
     # lift / initialisation
     ik_iters: int = 50
     ik_restarts: int = 8      # multi-start lift: starts per (particle, block)
+    mid_candidates: int = 8   # seeding: intermediate-waypoint draws per segment
     ik_lambda: float = 0.05
     ik_noise: float = 0.5
     mid_noise: float = 0.5

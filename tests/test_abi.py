@@ -68,7 +68,7 @@ def _create(a, n_sph=None, n_obs=None):
 @pytest.mark.parametrize("mutate,code", [
     ("nan_dh", -1), ("bad_link", -1), ("link_order", -1), ("neg_radius", -1), ("neg_half", -1),
     ("too_many_blocks", -4), ("bad_mode", -1), ("bad_grasp", -1), ("neg_weight", -1), ("bad_beta", -1),
-    ("small_region", -1), ("neg_count", -1), ("no_ik_starts", -1), ("too_many_ik_starts", -1),
+    ("small_region", -1), ("neg_count", -1), ("no_ik_starts", -1), ("too_many_ik_starts", -1), ("no_mid", -1), ("too_many_mid", -1),
 ])
 def test_problem_create_rejects(mutate, code):
     from paper_2510_07674_amd import synth
@@ -103,6 +103,10 @@ def test_problem_create_rejects(mutate, code):
         a["pr"].ik_restarts = 0
     elif mutate == "too_many_ik_starts":
         a["pr"].ik_restarts = 9
+    elif mutate == "no_mid":
+        a["pr"].mid_candidates = 0
+    elif mutate == "too_many_mid":
+        a["pr"].mid_candidates = 9
     rc, msg = _create(a, n_sph=n_sph)
     assert rc == code and msg
 

@@ -472,7 +472,18 @@ def test_traj_init_parity(sp, orc):
         qp = f32(rng.uniform(-2.5, 2.5, (P, prob.B, 7)))
         q32 = N(dev.traj_init(T(qg), T(qp), W, seed=77))
         q64 = o.traj_init(qg, qp, W, seed=77)
-        assert np.abs(q32 - q64).max() <= 2e-6
+        # the intermediate-waypoint draw is chosen by a penetration score; FP32 and FP64
+        # may choose differently only where two draws score the same within rounding
+        m = (W - 1) // 2
+        same = np.abs(q32 - q64).max(axis=(2, 3)) <= 2e-6
+        for p, s in zip(*np.nonzero(~same)):
+            pen32 = o.arm_obstacle_pen(q32[p, s, m].astype(np.float64))
+            pen64 = o.arm_obstacle_pen(q64[p, s, m])
+            qa, qb = q64[p, s, 0], q64[p, s, W - 1]
+            sc = lambda qm: (o.arm_obstacle_pen(qm) + o.arm_obstacle_pen(0.5 * (qa + qm)) +
+                             o.arm_obstacle_pen(0.5 * (qm + qb)))
+            assert sc(q32[p, s, m].astype(np.float64)) <= sc(q64[p, s, m]) + 1e-4, (p, s, pen32, pen64)
+        assert same.mean() >= 0.9
         assert np.array_equal(q32[:, :-1, W - 1], q32[:, 1:, 0])
 
 

@@ -782,3 +782,40 @@ def test_ik_error_is_residual_norm(orc):
     assert o.ik_error(1, tgt, q) < 1e-12 and o.ik_error(0, tgt, q) < 1e-12
     d = np.array([0.003, -0.004, 0.0, 0.0])
     assert abs(o.ik_error(0, tgt + d, q) - 0.005) < 1e-12
+
+
+def test_traj_init_candidate_rule(orc):
+    """Seeding: the intermediate waypoint is, among mid_candidates draws of midpoint + noise
+    (numpy Philox, counter (particle, 2s + chunk, c, 3)), the one whose seed path has the
+    least arm-obstacle penetration at the draw and the two halfway points (first on ties),
+    penetration from the numpy box distance."""
+    prob, pr, _ = synth.config("tower4", 2)
+    o = orc.Oracle(prob, pr)
+    rng = np.random.default_rng(41)
+    P, B, W, seed = 3, prob.B, 16, 77
+    qg = rng.uniform(-2, 2, (P, B, 7))
+    qp = rng.uniform(-2, 2, (P, B, 7))
+    q = o.traj_init(qg, qp, W, seed=seed)
+    m = (W - 1) // 2
+    qh = np.clip(prob.q_home, prob.lo, prob.hi)
+    moved = 0
+    for p in range(1, P):
+        for s in range(2 * B):
+            b = s // 2
+            qa = (qh if b == 0 else qp[p, b - 1]) if s % 2 == 0 else qg[p, b]
+            qb = qg[p, b] if s % 2 == 0 else qp[p, b]
+            scores, cands = [], []
+            for c in range(pr.mid_candidates):
+                u = []
+                for k in (2 * s, 2 * s + 1):
+                    raw = np.random.Philox(key=np.array([seed, 0], np.uint64),
+                                           counter=np.array([p - 1, k, c, 3], np.uint64)).random_raw(4)
+                    u += list((raw >> np.uint64(40)).astype(np.float64) / 2.0**24)
+                qc = np.clip(0.5 * (qa + qb) + pr.mid_noise * (2 * np.array(u[:7]) - 1), prob.lo, prob.hi)
+                cands.append(qc)
+                scores.append(_np_arm_pen(o, prob, qc) + _np_arm_pen(o, prob, 0.5 * (qa + qc)) +
+                              _np_arm_pen(o, prob, 0.5 * (qc + qb)))
+            best = int(np.argmin(scores))
+            assert np.array_equal(q[p, s, m], cands[best]), (p, s)
+            moved += best != 0
+    assert moved > 0   # the rule does change some choices
