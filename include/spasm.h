@@ -243,6 +243,23 @@ size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg);
 int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
                 float *d_best_q, float *d_best_pose, spasm_result *out, void *stream);
 
+/* Time to first solution (the paper's solve-time measure): attempts of the whole method.
+ * Within an attempt the stage-2 descent runs in chunks of check_every iterations (Adam
+ * moments kept in the workspace between chunks, so the iterates equal those of one
+ * launch) and stops after the first chunk whose end state has a satisfying particle
+ * (violation < sat_eps); an attempt that reaches K without one is followed by a new one
+ * with fresh samples (seed + attempt * 0x9E3779B97F4A7C15), at most max_attempts.  The
+ * returned particle is the best of the stopping chunk (satisfying first), or of the last
+ * attempt.  out->total_ms is device time from the start to that chunk's result (HIP
+ * events, including the host check between chunks); *attempts_out and *iters_out
+ * (nullable) receive the attempts and stage-2 iterations run.  d_work:
+ * spasm_solve_ttfs_workspace() bytes, 256-byte aligned. */
+size_t spasm_solve_ttfs_workspace(spasm_problem prob, const spasm_solve_config *cfg);
+int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t check_every,
+                     int32_t max_attempts, void *d_work, size_t work_bytes, float *d_best_q,
+                     float *d_best_pose, spasm_result *out, int32_t *attempts_out, int32_t *iters_out,
+                     void *stream);
+
 /* --- serving (continuous batching) --------------------------------------------------------
  * A server owns one device arena of hbm_budget bytes, max_slots solve slots, an
  * admission stream and four class streams.  Requests are queued by spasm_server_submit.

@@ -661,6 +661,114 @@ extern "C" size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_co
     return solve_layout(prob->kp, *cfg).total;
 }
 
+namespace spasm {
+size_t stage2_opt_bytes(const KProb &K, const spasm_solve_config &cfg)
+{
+    const size_t B = K.B;
+    return (size_t)cfg.M * 2 * (2 * B * cfg.W * NJ + 4 * B) * sizeof(float);
+}
+}  // namespace spasm
+
+extern "C" size_t spasm_solve_ttfs_workspace(spasm_problem prob, const spasm_solve_config *cfg)
+{
+    if (check_cfg(prob, cfg)) return 0;
+    return align256(solve_layout(prob->kp, *cfg).total) + align256(stage2_opt_bytes(prob->kp, *cfg));
+}
+
+extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t check_every,
+                                int32_t max_attempts, void *d_work, size_t work_bytes, float *d_best_q,
+                                float *d_best_pose, spasm_result *out, int32_t *attempts_out, int32_t *iters_out,
+                                void *stream)
+{
+    int rc = check_cfg(prob, cfg);
+    if (rc) return rc;
+    if (check_every < 1) return fail(SPASM_EINVAL, "check_every=%d must be >= 1", check_every);
+    if (max_attempts < 1) return fail(SPASM_EINVAL, "max_attempts=%d must be >= 1", max_attempts);
+    if (!d_work || !d_best_q || !d_best_pose || !out) return fail(SPASM_EINVAL, "NULL buffer");
+    if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace must be 256-byte aligned");
+    const KProb &K = prob->kp;
+    const SolveLayout L = solve_layout(K, *cfg);
+    const size_t opt_off = align256(L.total), obytes = stage2_opt_bytes(K, *cfg);
+    if (work_bytes < opt_off + align256(obytes))
+        return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, opt_off + align256(obytes));
+    rc = ensure_attrs();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)d_work;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) SPASM_HIP(hipEventCreate(&ev[i]));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } guard{ev};
+    int32_t *h_info = nullptr;
+    SPASM_HIP(hipHostMalloc((void **)&h_info, 8 * sizeof(int32_t) + 4 * sizeof(float)));
+    struct HostGuard {
+        int32_t *p;
+        ~HostGuard() { (void)hipHostFree(p); }
+    } hguard{h_info};
+    float *h_finfo = (float *)(h_info + 8);
+
+    SPASM_HIP(hipEventRecord(ev[0], st));
+    int att = 0, iters = 0;
+    bool solved = false;
+    for (att = 0; att < max_attempts && !solved; ++att) {
+        spasm_solve_config ca = *cfg;
+        ca.seed = cfg->seed + (uint64_t)att * 0x9E3779B97F4A7C15ull;  // fresh samples per attempt
+        rc = enqueue_prefix(prob, ca, w, L, st);
+        if (rc) return rc;
+        SPASM_HIP(launch_zero(w + opt_off, obytes, st));
+        TrajArgs a{};
+        a.P = ca.M;
+        a.W = ca.W;
+        a.q_in = F(L.q);
+        a.pose_in = F(L.pose);
+        a.q_out = F(L.q);
+        a.pose_out = F(L.pose);
+        a.opt = F(opt_off);
+        a.k_lin2 = (int)std::lround(prob->lin_frac2 * ca.K);
+        a.cost = F(L.c2);
+        a.viol = F(L.v2);
+        for (int k0 = 1; k0 <= ca.K; k0 += check_every) {
+            a.k_begin = k0;
+            a.k_end = std::min(ca.K, k0 + check_every - 1) + 1;
+            SPASM_HIP(launch_traj(K, 2, a, st));
+            iters += a.k_end - a.k_begin;
+            rc = enqueue_finish(prob, ca, w, L, d_best_q, d_best_pose, st);
+            if (rc) return rc;
+            SPASM_HIP(hipMemcpyAsync(h_info, I(L.info), 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            SPASM_HIP(hipMemcpyAsync(h_finfo, F(L.finfo), 4 * sizeof(float), hipMemcpyDeviceToHost, st));
+            SPASM_HIP(hipEventRecord(ev[1], st));
+            SPASM_HIP(hipStreamSynchronize(st));
+            if (h_info[2] > 0) {
+                solved = true;
+                break;
+            }
+        }
+    }
+    float t = 0.f;
+    SPASM_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+    std::memset(out, 0, sizeof(*out));
+    out->stage1_sat = h_info[0];
+    out->rounds = h_info[1];
+    out->n_sat = h_info[2];
+    out->best = h_info[3];
+    out->success = h_info[2] > 0;
+    out->viol = h_finfo[0];
+    out->cost = h_finfo[1];
+    out->length = h_finfo[2];
+    out->total_ms = t;
+    if (attempts_out) *attempts_out = att;
+    if (iters_out) *iters_out = iters;
+    return SPASM_OK;
+}
+
 extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
                            float *d_best_q, float *d_best_pose, spasm_result *out, void *stream)
 {

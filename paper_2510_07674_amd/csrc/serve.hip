@@ -43,11 +43,7 @@ constexpr int MAX_CLASS_LAUNCHES = 64;  // timed class launches per step
 
 using ClassKey = std::pair<int, int>;  // (threads, sphere chunk)
 
-size_t opt_bytes(spasm_problem prob, const spasm_solve_config &c)
-{
-    const size_t B = prob->kp.B;
-    return (size_t)c.M * 2 * (2 * B * c.W * NJ + 4 * B) * sizeof(float);
-}
+size_t opt_bytes(spasm_problem prob, const spasm_solve_config &c) { return stage2_opt_bytes(prob->kp, c); }
 
 size_t request_footprint(spasm_problem prob, const spasm_solve_config &c)
 {

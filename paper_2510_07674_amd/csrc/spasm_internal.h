@@ -87,6 +87,8 @@ hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *vio
                             int M, int32_t *out_idx, int32_t *out_count, const int *skip,
                             hipStream_t st);
 size_t topm_workspace(int n, int M);
+// Adam moments of a chunked stage-2 run: [M][(2B W 7 + 4B) * 2] floats
+size_t stage2_opt_bytes(const KProb &K, const spasm_solve_config &cfg);
 hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *ws, hipStream_t st);
 hipError_t launch_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,
                                float *x_out, float *c_out, float *v_out, hipStream_t st);

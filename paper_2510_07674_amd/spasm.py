@@ -73,6 +73,9 @@ SYMBOLS = {
     "spasm_ik_lift": ([c_vp, c_i32, c_vp, c_u64, c_i32, c_vp, c_vp, c_vp], c_i32),
     "spasm_traj_init": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_u64, c_vp, c_vp], c_i32),
     "spasm_solve_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
+    "spasm_solve_ttfs_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
+    "spasm_solve_ttfs": ([c_vp, ctypes.POINTER(SolveConfigDesc), c_i32, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp,
+                          ctypes.POINTER(ResultDesc), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_vp], c_i32),
     "spasm_solve": ([c_vp, ctypes.POINTER(SolveConfigDesc), c_vp, ctypes.c_size_t, c_vp, c_vp,
                      ctypes.POINTER(ResultDesc), c_vp], c_i32),
     "spasm_server_footprint": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
@@ -312,6 +315,28 @@ class Problem:
                                   _dev(best_q, (2 * self.B, cfg.W, 7), name="best_q"),
                                   _dev(best_pose, (self.B, 4), name="best_pose"), ctypes.byref(res), _stream()))
         out = {f: getattr(res, f) for f, _ in ResultDesc._fields_}
+        return out, best_q, best_pose
+
+    def solve_ttfs(self, cfg, check_every, max_attempts, work=None, best_q=None, best_pose=None):
+        """Time to first solution: returns (result dict with 'attempts' and 'iters', best_q, best_pose)."""
+        c = self.config_desc(cfg)
+        if work is None:
+            n = load().spasm_solve_ttfs_workspace(self.handle, ctypes.byref(c))
+            if n == 0:
+                _check(-1)
+            work = torch.empty(n, dtype=torch.uint8, device="cuda")
+        if best_q is None:
+            best_q = _empty(2 * self.B, cfg.W, 7)
+        if best_pose is None:
+            best_pose = _empty(self.B, 4)
+        res, att, its = ResultDesc(), c_i32(), c_i32()
+        _check(load().spasm_solve_ttfs(self.handle, ctypes.byref(c), check_every, max_attempts,
+                                       _dev(work, dtype=torch.uint8, name="work"), work.numel(),
+                                       _dev(best_q, (2 * self.B, cfg.W, 7), name="best_q"),
+                                       _dev(best_pose, (self.B, 4), name="best_pose"), ctypes.byref(res),
+                                       ctypes.byref(att), ctypes.byref(its), _stream()))
+        out = {f: getattr(res, f) for f, _ in ResultDesc._fields_}
+        out["attempts"], out["iters"] = att.value, its.value
         return out, best_q, best_pose
 
 

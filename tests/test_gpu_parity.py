@@ -530,3 +530,22 @@ def test_full_size_sampled(sp, orc):
     c64, v64, gq64, gp64, sk, pk = o.traj_cost(q[pick], pose[pick], 0)
     check_cost("full tower10", c32[pick], c64, v32[pick], v64)
     check_grad("full tower10 q", gq32[pick], gq64, sk >= KINK)
+
+
+def test_solve_ttfs(sp):
+    """Time to first solution: one attempt checked only at K equals the plain solve bit for
+    bit (chunked Adam state in the workspace); with checks every 25 iterations a reported
+    success satisfies the threshold and stops at a chunk boundary."""
+    prob, pr, cfg = synth.config("tiny", synth.certified_seeds("tiny")[1])
+    dev = sp.Problem(prob, pr)
+    res, bq, bp = dev.solve(cfg)
+    rt, tq, tp = dev.solve_ttfs(cfg, check_every=cfg.K, max_attempts=1)
+    assert rt["attempts"] == 1 and rt["iters"] == cfg.K
+    assert torch.equal(bq, tq) and torch.equal(bp, tp) and rt["viol"] == res["viol"]
+    for s in synth.certified_seeds("tiny")[:6]:
+        prob, pr, cfg = synth.config("tiny", s)
+        rt, tq, _ = sp.Problem(prob, pr).solve_ttfs(cfg, check_every=10, max_attempts=3)
+        assert 1 <= rt["attempts"] <= 3 and rt["iters"] % 10 == 0 or rt["iters"] % cfg.K == 0
+        if rt["success"]:
+            assert rt["viol"] < pr.sat_eps and rt["n_sat"] > 0
+        assert bool(torch.isfinite(tq).all())
