@@ -66,7 +66,7 @@ def cpu_baseline(name, seconds):
     x = synth.clustered_placements(rng, prob, P, spread=0.01)
     pose = o.initial_poses(x)
     qg, qp = o.ik_lift(pose, seed=0)
-    q = o.traj_init(qg, qp, W, seed=0)
+    q = o.traj_init(qg, qp, W, seed=0, pose=pose)
     mq, vq, mp, vp = (np.zeros_like(q), np.zeros_like(q), np.zeros_like(pose), np.zeros_like(pose))
     k, t0 = 0, time.perf_counter()
     while True:

@@ -213,9 +213,8 @@ int spasm_place_round(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, i
  *   Place at d_pose[p][b]: start 0 from the chosen grasp solution, start r >= 1 uniform
  *   (counter (particle, 2B + 2b + chunk, r, 2)).  Among the starts whose final error |e|
  *   (position and orientation error of the iteration) is below 1e-4 each solve keeps the
- *   one with the smallest arm-obstacle penetration (sum over robot spheres and boxes of
- *   max(0, r - sdf); the first on ties); when none converged, the start with the smallest
- *   error (the first on ties).
+ *   one with the smallest clutter score (see spasm_traj_init; the first on ties); when
+ *   none converged, the start with the smallest error (the first on ties).
  *   d_qgrasp, d_qplace [P][B][7]. */
 int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, const float *d_target, float *d_q,
                      int32_t iters, void *stream);
@@ -226,10 +225,16 @@ int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose, uint64_t s
  * the first segment starts at q_home.  The intermediate waypoint is the best of
  * mid_candidates draws c of the segment ends' midpoint plus mid_noise U[-1,1]^7 (counter
  * (particle, 2s + chunk, c, 3)), clamped to the limits: the draw whose seed path has the
- * smallest arm-obstacle penetration sum at the intermediate waypoint and at the two
- * points halfway to the ends (the first on ties).  d_q [P][2B][W][7]. */
+ * smallest clutter score (below) summed at the intermediate waypoint and at the two
+ * points halfway to the ends (the first on ties).  d_pose [P][B][4]: the placements.
+ * d_q [P][2B][W][7].
+ * Clutter score of q for block b (also used by the lift): the sum over robot spheres of
+ * max(0, r - sdf) against every box and every block visible as in the stage-2 cost --
+ * blocks below b at their placements, above b at their initial poses, block b at its
+ * placement for a place configuration, at its initial pose inside its transit, not at
+ * the grasp nor while held. */
 int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgrasp,
-                    const float *d_qplace, uint64_t seed, float *d_q, void *stream);
+                    const float *d_qplace, const float *d_pose, uint64_t seed, float *d_q, void *stream);
 
 /* --- whole method ------------------------------------------------------------------------
  * Stage 1 (cfg->N1 > 0): sample N1, score (linear phase), keep the best M, descend,

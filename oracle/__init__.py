@@ -73,9 +73,9 @@ def lib():
         L.or_ik_lift.argtypes = [P, i, vp, u64, i, d, d, i, vp, vp]
         L.or_ik_error.argtypes = [P, i, vp, vp]
         L.or_ik_error.restype = d
-        L.or_arm_obstacle_pen.argtypes = [P, vp]
-        L.or_arm_obstacle_pen.restype = d
-        L.or_traj_init.argtypes = [P, i, i, vp, vp, u64, d, i, vp]
+        L.or_arm_clutter.argtypes = [P, vp, vp, i, i]
+        L.or_arm_clutter.restype = d
+        L.or_traj_init.argtypes = [P, i, i, vp, vp, vp, u64, d, i, vp]
         L.or_stage1.argtypes = [P, i, i, u64, i, i, i, d, d, vp, vp, vp]
         L.or_stage2.argtypes = [P, i, i, i, i, d, d, d, d, d, vp, vp]
         _lib = L
@@ -191,9 +191,11 @@ class Oracle:
         """|e| of the IK iteration at q (position and orientation error of the block frame)."""
         return lib().or_ik_error(self.ref, kind, _ptr(_f64(target)), _ptr(_f64(q)))
 
-    def arm_obstacle_pen(self, q):
-        """Sum over robot spheres and boxes of max(0, r - sdf) at the configuration q."""
-        return lib().or_arm_obstacle_pen(self.ref, _ptr(_f64(q)))
+    def arm_clutter(self, q, pose, b, kind):
+        """Arm clutter score at q for block b: sum over robot spheres of max(0, r - sdf)
+        against the boxes and the blocks visible in situation kind (0 grasp, 1 place,
+        2 transit interior, 3 transfer interior); pose [B, 4] the particle's placements."""
+        return lib().or_arm_clutter(self.ref, _ptr(_f64(q)), _ptr(_f64(pose)), b, kind)
 
     def ik_lift(self, pose, seed, iters=None):
         pose = _f64(pose)
@@ -204,11 +206,13 @@ class Oracle:
                          pr.ik_lambda, pr.ik_noise, pr.ik_restarts, _ptr(qg), _ptr(qp))
         return qg, qp
 
-    def traj_init(self, qg, qp, W, seed):
-        qg, qp = _f64(qg), _f64(qp)
+    def traj_init(self, qg, qp, W, seed, pose):
+        """Seeds; pose [P, B, 4] the placements (the intermediate-waypoint choice sees the
+        blocks at them)."""
+        qg, qp, pose = _f64(qg), _f64(qp), _f64(pose)
         P, B = qg.shape[:2]
         q = np.zeros((P, 2 * B, W, 7))
-        lib().or_traj_init(self.ref, P, W, _ptr(qg), _ptr(qp), seed, self.params.mid_noise,
+        lib().or_traj_init(self.ref, P, W, _ptr(qg), _ptr(qp), _ptr(pose), seed, self.params.mid_noise,
                            self.params.mid_candidates, _ptr(q))
         return q
 
@@ -253,7 +257,7 @@ class Oracle:
             nsat = -1
             pose = np.repeat(_f64(prob.goal)[None], cfg.M, axis=0)
         qg, qp = self.ik_lift(pose, cfg.seed)
-        q = self.traj_init(qg, qp, cfg.W, cfg.seed)
+        q = self.traj_init(qg, qp, cfg.W, cfg.seed, pose)
         q, pose = self.stage2(q, pose, cfg.K)
         cost, viol = self.traj_cost(q, pose, phase=QUAD, grad=False)[:2]
         order2, nsat2 = self.order(cost, viol)

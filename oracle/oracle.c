@@ -858,18 +858,35 @@ void or_ik_iterate(const or_problem *pb, int kind, const double *target, double 
     }
 }
 
-/* Sum over the robot spheres and obstacle boxes of max(0, r - sdf) at q: how deep the
- * arm stands in the clutter. */
-double or_arm_obstacle_pen(const or_problem *pb, const double *q)
+/* How deep the arm stands in the clutter at q, for block b in situation `kind`: the sum
+ * over robot spheres of max(0, r - sdf) against every box and every block visible there
+ * (as in the stage-2 cost): blocks below b at their placements pose[bb], blocks above b at
+ * their initial poses, and block b itself at its placement after the place (kind 1), at
+ * its initial pose inside its transit (kind 2), not at the grasp (kind 0) nor while held
+ * (kind 3). */
+double or_arm_clutter(const or_problem *pb, const double *q, const double *pose, int b, int kind)
 {
     frame F[9];
     fk_frames(pb, q, F);
+    const double half = 0.5 * pb->h;
     double pen = 0.0;
     for (int i = 0; i < pb->S; ++i) {
-        double c[3], g[3];
+        double c[3], g[3], gpo[4];
         apply(&F[pb->sph_link[i]], pb->sph_c + 3 * i, c);
+        const double r = pb->sph_r[i];
         for (int o = 0; o < pb->O; ++o) {
-            const double d = pb->sph_r[i] - box_sdf_ex(c, pb->boxes + 6 * o, g, NULL);
+            const double d = r - box_sdf_ex(c, pb->boxes + 6 * o, g, NULL);
+            if (d > 0.0) pen += d;
+        }
+        for (int bb = 0; bb < pb->B; ++bb) {
+            const double *bp;
+            if (bb < b || (bb == b && kind == 1))
+                bp = pose + 4 * bb;
+            else if (bb > b || (bb == b && kind == 2))
+                bp = pb->block_init + 4 * bb;
+            else
+                continue;
+            const double d = r - obb_sdf_ex(c, bp, half, g, gpo, NULL);
             if (d > 0.0) pen += d;
         }
     }
@@ -883,7 +900,8 @@ double or_arm_obstacle_pen(const or_problem *pb, const double *q)
  * the smallest error (the first on ties). */
 #define OR_IK_ACCEPT 1e-4
 static void ik_multistart(const or_problem *pb, int kind, const double *target, const double *q0, uint64_t seed,
-                          int p, int sub, int restarts, int iters, double lambda, double *q_out)
+                          int p, int sub, int restarts, int iters, double lambda, const double *pose, int b,
+                          double *q_out)
 {
     double best_err = INFINITY, best_pen = INFINITY;
     int have_acc = 0;
@@ -900,7 +918,7 @@ static void ik_multistart(const or_problem *pb, int kind, const double *target, 
         or_ik_iterate(pb, kind, target, q, iters, lambda);
         const double err = or_ik_error(pb, kind, target, q);
         if (err < OR_IK_ACCEPT) {
-            const double pen = or_arm_obstacle_pen(pb, q);
+            const double pen = or_arm_clutter(pb, q, pose, b, kind);
             if (!have_acc || pen < best_pen) {
                 have_acc = 1;
                 best_pen = pen;
@@ -930,10 +948,10 @@ void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, 
             for (int j = 0; j < NJ; ++j)
                 q0[j] = clampd(pb->q_home[j] + noise * (2.0 * u[j] - 1.0), pb->lo[j], pb->hi[j]);
             double *g = q_grasp + ((size_t)p * B + b) * NJ;
-            ik_multistart(pb, 0, pb->block_init + 4 * b, q0, seed, p, 2 * b, restarts, iters, lambda, g);
+            const double *pp = pose + (size_t)p * B * 4;
+            ik_multistart(pb, 0, pb->block_init + 4 * b, q0, seed, p, 2 * b, restarts, iters, lambda, pp, b, g);
             double *pl = q_place + ((size_t)p * B + b) * NJ;
-            ik_multistart(pb, 1, pose + ((size_t)p * B + b) * 4, g, seed, p, 2 * B + 2 * b, restarts, iters,
-                          lambda, pl);
+            ik_multistart(pb, 1, pp + 4 * b, g, seed, p, 2 * B + 2 * b, restarts, iters, lambda, pp, b, pl);
         }
 }
 
@@ -943,7 +961,7 @@ void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, 
  * uniform noise (see below).  The first segment starts at q_home.  Segment ends are
  * copied exactly so that the shared boundary configurations are equal. */
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, const double *q_place,
-                  uint64_t seed, double noise, int candidates, double *q)
+                  const double *pose, uint64_t seed, double noise, int candidates, double *q)
 {
     const int B = pb->B, NS = 2 * B, m = (W - 1) / 2;
     double qh[NJ];
@@ -972,8 +990,11 @@ void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, con
                     h1[j] = 0.5 * (qa[j] + qc[j]);
                     h2[j] = 0.5 * (qc[j] + qb[j]);
                 }
-                const double sc = candidates > 1 ? or_arm_obstacle_pen(pb, qc) + or_arm_obstacle_pen(pb, h1) +
-                                                       or_arm_obstacle_pen(pb, h2)
+                const double *pp = pose + (size_t)p * B * 4;
+                const int kind = 2 + s % 2;  /* transit or transfer interior */
+                const double sc = candidates > 1 ? or_arm_clutter(pb, qc, pp, b, kind) +
+                                                       or_arm_clutter(pb, h1, pp, b, kind) +
+                                                       or_arm_clutter(pb, h2, pp, b, kind)
                                                  : 0.0;
                 if (c == 0 || sc < best) {
                     best = sc;

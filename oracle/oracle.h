@@ -57,11 +57,12 @@ void or_order(int n, const double *cost, const double *viol, double eps, int32_t
 void or_ik_iterate(const or_problem *pb, int kind, const double *target, double *q,
                    int iters, double lambda);
 double or_ik_error(const or_problem *pb, int kind, const double *target, const double *q);
-double or_arm_obstacle_pen(const or_problem *pb, const double *q);
+double or_arm_clutter(const or_problem *pb, const double *q, const double *pose, int b, int kind);
 void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, int iters,
                 double lambda, double noise, int restarts, double *q_grasp, double *q_place);
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp,
-                  const double *q_place, uint64_t seed, double noise, int candidates, double *q);
+                  const double *q_place, const double *pose, uint64_t seed, double noise,
+                  int candidates, double *q);
 void or_stage1(const or_problem *pb, int N, int M, uint64_t seed, int round, int k_lin,
                int k_quad, double eta, double alpha, double *x_out, double *cost_out,
                double *viol_out);

@@ -530,13 +530,13 @@ extern "C" int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose,
 }
 
 extern "C" int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgrasp, const float *d_qplace,
-                               uint64_t seed, float *d_q, void *stream)
+                               const float *d_pose, uint64_t seed, float *d_q, void *stream)
 {
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
     int rc = check_traj_shape(prob, P, W);
     if (rc) return rc;
-    if (!d_qgrasp || !d_qplace || !d_q) return fail(SPASM_EINVAL, "NULL buffer");
-    SPASM_HIP(launch_traj_init(prob->kp, P, W, d_qgrasp, d_qplace, seed, d_q, (hipStream_t)stream));
+    if (!d_qgrasp || !d_qplace || !d_pose || !d_q) return fail(SPASM_EINVAL, "NULL buffer");
+    SPASM_HIP(launch_traj_init(prob->kp, P, W, d_qgrasp, d_qplace, d_pose, seed, d_q, (hipStream_t)stream));
     return SPASM_OK;
 }
 
@@ -638,7 +638,7 @@ int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, c
     }
     if (after_stage1) SPASM_HIP(hipEventRecord(after_stage1, st));
     SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg.seed, prob->ik_iters, F(L.qg), F(L.qp), st));
-    SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), cfg.seed, F(L.q), st));
+    SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), F(L.pose), cfg.seed, F(L.q), st));
     return SPASM_OK;
 }
 

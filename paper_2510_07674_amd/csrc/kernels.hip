@@ -1416,13 +1416,18 @@ __global__ void k_ik_iterate(KProb P, int kind, int n, const float *target, floa
     for (int j = 0; j < NJ; ++j) qio[(size_t)gid * NJ + j] = q[j];
 }
 
-// Sum over the robot spheres and obstacle boxes of max(0, r - sdf) at q (dense: it runs
-// once per IK start).  Padded spheres (r = -1e30) contribute nothing.
-__device__ __forceinline__ float arm_obstacle_pen(const KProb &P, const float (&q)[NJ])
+// How deep the arm stands in the clutter at q, for block b in situation kind (0 grasp,
+// 1 place, 2 transit interior, 3 transfer interior): the sum over robot spheres of
+// max(0, r - sdf) against every box and every block visible there -- blocks below b at
+// their placements pose[bb], blocks above b at their initial poses, block b itself at its
+// placement after the place and at its initial pose inside its transit.  Dense: it runs
+// once per IK start or seed candidate.  Padded spheres (r = -1e30) contribute nothing.
+__device__ __forceinline__ float arm_clutter(const KProb &P, const float (&q)[NJ], const float *pose, int b, int kind)
 {
     Frame F;
     frame_identity(F);
     float pen = 0.f;
+    const float half = P.half;
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {
         dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
@@ -1434,6 +1439,31 @@ __device__ __forceinline__ float arm_obstacle_pen(const KProb &P, const float (&
             for (int o = 0; o < P.O; ++o) {
                 const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
                 const float ux = fabsf(cx - bc.x) - be.x, uy = fabsf(cy - bc.y) - be.y, uz = fabsf(cz - bc.z) - be.z;
+                const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
+                const float sdf = __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz) + fminf(fmaxf(fmaxf(ux, uy), uz), 0.f);
+                pen += fmaxf(sp.w - sdf, 0.f);
+            }
+            for (int bb = 0; bb < P.B; ++bb) {
+                float tx, ty, tz, yaw;
+                if (bb < b || (bb == b && kind == 1)) {
+                    tx = pose[4 * bb];
+                    ty = pose[4 * bb + 1];
+                    tz = pose[4 * bb + 2];
+                    yaw = pose[4 * bb + 3];
+                } else if (bb > b || (bb == b && kind == 2)) {
+                    const float4 I = ldc(P.blk_init, 2 * bb);
+                    tx = I.x;
+                    ty = I.y;
+                    tz = I.z;
+                    yaw = I.w;
+                } else {
+                    continue;
+                }
+                float sn, cs;
+                sincosf(yaw, &sn, &cs);
+                const float dx = cx - tx, dy = cy - ty, dz = cz - tz;
+                const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
+                const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
                 const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
                 const float sdf = __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz) + fminf(fmaxf(fmaxf(ux, uy), uz), 0.f);
                 pen += fmaxf(sp.w - sdf, 0.f);
@@ -1483,7 +1513,7 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     if (r < R) {
         ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
         err = ik_error(P, 0, I.x, I.y, I.z, 0.f, q);
-        if (err < 1e-4f) pen = arm_obstacle_pen(P, q);
+        if (err < 1e-4f) pen = arm_clutter(P, q, pose + (size_t)p * B * 4, b, 0);
     }
     int src = ik_pick(err, pen, r, R);
     float qc[NJ];
@@ -1503,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     if (r < R) {
         ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
         err = ik_error(P, 1, t[0], t[1], t[2], t[3], q);
-        if (err < 1e-4f) pen = arm_obstacle_pen(P, q);
+        if (err < 1e-4f) pen = arm_clutter(P, q, pose + (size_t)p * B * 4, b, 1);
     }
     src = ik_pick(err, pen, r, R);
 #pragma unroll
@@ -1536,7 +1566,7 @@ __device__ __forceinline__ void segment_ends(const KProb &P, const float *qg, co
 // scores the seed path by arm-obstacle penetration at the draw and at the two points
 // halfway to the ends; the lowest score (first on ties) is written to waypoint (W-1)/2.
 __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const float *qg, const float *qp,
-                                                  uint64_t seed, float *q)
+                                                  const float *pose, uint64_t seed, float *q)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int grp = gid >> 3, c = gid & 7, NS = 2 * P.B, C = P.mid_candidates;
@@ -1553,7 +1583,13 @@ __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const 
         h2[j] = 0.5f * (qc[j] + qb[j]);
     }
     float sc = INFINITY;
-    if (c < C) sc = C > 1 ? arm_obstacle_pen(P, qc) + arm_obstacle_pen(P, h1) + arm_obstacle_pen(P, h2) : 0.f;
+    if (c < C) {
+        const float *pp = pose + (size_t)p * P.B * 4;
+        const int kind = 2 + (s & 1);  // transit or transfer interior
+        sc = C > 1 ? arm_clutter(P, qc, pp, s >> 1, kind) + arm_clutter(P, h1, pp, s >> 1, kind) +
+                         arm_clutter(P, h2, pp, s >> 1, kind)
+                   : 0.f;
+    }
     const int lane = threadIdx.x & 63, g0 = lane & ~7;
     const float best = group8_reduce(sc, OpMin());
     const int src = g0 + __builtin_ctzll((__ballot(c < C && sc == best) >> g0) & 0xFFull);
@@ -1836,11 +1872,12 @@ hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t se
     return hipGetLastError();
 }
 
-hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q,
-                            hipStream_t st)
+hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, const float *pose,
+                            uint64_t seed, float *q, hipStream_t st)
 {
     const long g = (long)nP * 2 * P.B * 8;
-    hipLaunchKernelGGL(k_seed_mid, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, P, nP, W, qg, qp, seed, q);
+    hipLaunchKernelGGL(k_seed_mid, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, P, nP, W, qg, qp, pose, seed,
+                       q);
     const int n = nP * 2 * P.B * W;
     hipLaunchKernelGGL(k_traj_init, dim3((n + 255) / 256), dim3(256), 0, st, P, nP, W, qg, qp, seed, q);
     return hipGetLastError();

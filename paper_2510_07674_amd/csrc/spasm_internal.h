@@ -97,7 +97,7 @@ hipError_t launch_ik_iterate(const KProb &P, int kind, int n, const float *targe
                              int iters, hipStream_t st);
 hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t seed, int iters,
                           float *qg, float *qp, hipStream_t st);
-hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp,
+hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, const float *pose,
                             uint64_t seed, float *q, hipStream_t st);
 
 // solve glue

@@ -71,7 +71,7 @@ SYMBOLS = {
                           c_i32),
     "spasm_ik_iterate": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp], c_i32),
     "spasm_ik_lift": ([c_vp, c_i32, c_vp, c_u64, c_i32, c_vp, c_vp, c_vp], c_i32),
-    "spasm_traj_init": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_u64, c_vp, c_vp], c_i32),
+    "spasm_traj_init": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_u64, c_vp, c_vp], c_i32),
     "spasm_solve_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
     "spasm_solve_ttfs_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
     "spasm_solve_ttfs": ([c_vp, ctypes.POINTER(SolveConfigDesc), c_i32, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp,
@@ -278,11 +278,12 @@ class Problem:
                                     self.params.ik_iters if iters is None else iters, _dev(qg), _dev(qp), _stream()))
         return qg, qp
 
-    def traj_init(self, qg, qp, W, seed):
+    def traj_init(self, qg, qp, W, seed, pose):
         P = qg.shape[0]
         q = _empty(P, 2 * self.B, W, 7)
         _check(load().spasm_traj_init(self.handle, P, W, _dev(qg, (P, self.B, 7), name="qg"),
-                                      _dev(qp, (P, self.B, 7), name="qp"), seed, _dev(q), _stream()))
+                                      _dev(qp, (P, self.B, 7), name="qp"), _dev(pose, (P, self.B, 4), name="pose"),
+                                      seed, _dev(q), _stream()))
         return q
 
     # ---- whole method ----------------------------------------------------------------------

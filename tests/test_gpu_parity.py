@@ -137,7 +137,7 @@ def _states(kind, prob, pr, orc, rng, P, W):
         x = synth.clustered_placements(rng, prob, P, spread=0.01)
         pose = o.initial_poses(x)
     qg, qp = o.ik_lift(pose, seed=int(rng.integers(1000)))
-    return o.traj_init(qg, qp, W, seed=int(rng.integers(1000))), pose
+    return o.traj_init(qg, qp, W, seed=int(rng.integers(1000)), pose=pose), pose
 
 
 def _traj_parity(sp, orc, prob, pr, q, pose, label, phases=(0, 1)):
@@ -470,19 +470,21 @@ def test_traj_init_parity(sp, orc):
         P = 33
         qg = f32(rng.uniform(-2.5, 2.5, (P, prob.B, 7)))
         qp = f32(rng.uniform(-2.5, 2.5, (P, prob.B, 7)))
-        q32 = N(dev.traj_init(T(qg), T(qp), W, seed=77))
-        q64 = o.traj_init(qg, qp, W, seed=77)
-        # the intermediate-waypoint draw is chosen by a penetration score; FP32 and FP64
-        # may choose differently only where two draws score the same within rounding
+        if prob.mode == synth.MODE_FIXED:
+            pose = f32(np.repeat(prob.goal[None], P, axis=0))
+        else:
+            pose = f32(o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.05)))
+        q32 = N(dev.traj_init(T(qg), T(qp), W, seed=77, pose=T(pose)))
+        q64 = o.traj_init(qg, qp, W, seed=77, pose=pose)
+        # the intermediate-waypoint draw is chosen by a clutter score; FP32 and FP64 may
+        # choose differently only where two draws score the same within rounding
         m = (W - 1) // 2
         same = np.abs(q32 - q64).max(axis=(2, 3)) <= 2e-6
         for p, s in zip(*np.nonzero(~same)):
-            pen32 = o.arm_obstacle_pen(q32[p, s, m].astype(np.float64))
-            pen64 = o.arm_obstacle_pen(q64[p, s, m])
-            qa, qb = q64[p, s, 0], q64[p, s, W - 1]
-            sc = lambda qm: (o.arm_obstacle_pen(qm) + o.arm_obstacle_pen(0.5 * (qa + qm)) +
-                             o.arm_obstacle_pen(0.5 * (qm + qb)))
-            assert sc(q32[p, s, m].astype(np.float64)) <= sc(q64[p, s, m]) + 1e-4, (p, s, pen32, pen64)
+            qa, qb, kind = q64[p, s, 0], q64[p, s, W - 1], 2 + s % 2
+            sc = lambda qm: sum(o.arm_clutter(x, pose[p], s // 2, kind)
+                                for x in (qm, 0.5 * (qa + qm), 0.5 * (qm + qb)))
+            assert sc(q32[p, s, m].astype(np.float64)) <= sc(q64[p, s, m]) + 1e-4, (p, s)
         assert same.mean() >= 0.9
         assert np.array_equal(q32[:, :-1, W - 1], q32[:, 1:, 0])
 

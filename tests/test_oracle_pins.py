@@ -682,7 +682,8 @@ def test_traj_init_closed_form(orc):
     P, B, W = 3, prob.B, 16
     qg = rng.uniform(-2, 2, (P, B, 7))
     qp = rng.uniform(-2, 2, (P, B, 7))
-    q = o.traj_init(qg, qp, W, seed=5)
+    pose = o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.05))
+    q = o.traj_init(qg, qp, W, seed=5, pose=pose)
     m = (W - 1) // 2
     for p in range(P):
         assert np.array_equal(q[p, 0, 0], np.clip(prob.q_home, prob.lo, prob.hi))
@@ -700,27 +701,50 @@ def test_traj_init_closed_form(orc):
             assert np.all(np.abs(q[p, s, m] - 0.5 * (qa + end)) <= pr.mid_noise + 1e-12)
 
 
-def _np_arm_pen(o, prob, q):
-    """Sum of max(0, r - sdf) over robot spheres and boxes, box SDF written out in numpy."""
+def _np_clutter(o, prob, q, pose, b, kind):
+    """Clutter score written out in numpy: sum over robot spheres of max(0, r - sdf)
+    against the boxes and the blocks visible in situation kind (0 grasp, 1 place,
+    2 transit interior, 3 transfer interior)."""
     F = o.fk(q).reshape(9, 12)
     R, t = F[:, :9].reshape(9, 3, 3), F[:, 9:]
     c = np.einsum("sij,sj->si", R[prob.sph_link], prob.sph_c) + t[prob.sph_link]
     u = np.abs(c[:, None, :] - prob.boxes[None, :, :3]) - prob.boxes[None, :, 3:]
     sdf = np.linalg.norm(np.maximum(u, 0.0), axis=-1) + np.minimum(u.max(-1), 0.0)
-    return float(np.maximum(prob.sph_r[:, None] - sdf, 0.0).sum())
+    pen = float(np.maximum(prob.sph_r[:, None] - sdf, 0.0).sum())
+    half = prob.h / 2
+    for bb in range(prob.B):
+        if bb < b or (bb == b and kind == 1):
+            bp = pose[bb]
+        elif bb > b or (bb == b and kind == 2):
+            bp = prob.block_init[bb]
+        else:
+            continue
+        cs, sn = math.cos(bp[3]), math.sin(bp[3])
+        d = c - bp[:3]
+        loc = np.stack([cs * d[:, 0] + sn * d[:, 1], -sn * d[:, 0] + cs * d[:, 1], d[:, 2]], -1)
+        ub = np.abs(loc) - half
+        sd = np.linalg.norm(np.maximum(ub, 0.0), axis=-1) + np.minimum(ub.max(-1), 0.0)
+        pen += float(np.maximum(prob.sph_r - sd, 0.0).sum())
+    return pen
 
 
-def test_arm_obstacle_pen_matches_numpy(orc):
+def test_arm_clutter_matches_numpy(orc):
     prob, pr, _ = synth.config("tower4", 0)
     o = orc.Oracle(prob, pr)
     rng = np.random.default_rng(31)
+    pose = o.initial_poses(synth.clustered_placements(rng, prob, 1, spread=0.05))[0]
     deep = 0
-    for _ in range(40):
+    for i in range(60):
         q = rng.uniform(prob.lo, prob.hi)
-        ref = _np_arm_pen(o, prob, q)
-        assert o.arm_obstacle_pen(q) == pytest.approx(ref, rel=1e-12, abs=1e-14)
+        b, kind = i % prob.B, (i // prob.B) % 4
+        ref = _np_clutter(o, prob, q, pose, b, kind)
+        assert o.arm_clutter(q, pose, b, kind) == pytest.approx(ref, rel=1e-12, abs=1e-14)
         deep += ref > 0.0
     assert deep > 5   # the draw does reach into the clutter
+    # blocks count: a configuration inside block 1's initial volume scores less once block
+    # 1 is no longer visible (grasp of block 1) than inside its transit
+    scores = [o.arm_clutter(q, pose, 1, k) for k in (0, 2)]
+    assert scores[0] <= scores[1]
 
 
 def test_ik_lift_multistart_rule(orc):
@@ -743,12 +767,12 @@ def test_ik_lift_multistart_rule(orc):
             u += list((raw >> np.uint64(40)).astype(np.float64) / 2.0**24)
         return np.array(u[:7])
 
-    def pick(kind, target, starts):
+    def pick(kind, target, starts, p, b):
         sols = [o.ik_iterate(kind, target, q0, pr.ik_iters) for q0 in starts]
         errs = [o.ik_error(kind, target, q) for q in sols]
         acc = [i for i, e in enumerate(errs) if e < 1e-4]
         if acc:
-            pens = [_np_arm_pen(o, prob, sols[i]) for i in acc]
+            pens = [_np_clutter(o, prob, sols[i], pose[p], b, kind) for i in acc]
             return sols[acc[int(np.argmin(pens))]], True
         return sols[int(np.argmin(errs))], False
 
@@ -757,11 +781,11 @@ def test_ik_lift_multistart_rule(orc):
         for b in range(B):
             s0 = np.clip(prob.q_home + pr.ik_noise * (2 * u7(p, 2 * b, 0) - 1), prob.lo, prob.hi)
             starts = [s0] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * b, r) for r in range(1, pr.ik_restarts)]
-            g, ok_g = pick(0, prob.block_init[b], starts)
+            g, ok_g = pick(0, prob.block_init[b], starts, p, b)
             assert np.array_equal(g, qg[p, b])
             starts = [g] + [prob.lo + (prob.hi - prob.lo) * u7(p, 2 * B + 2 * b, r)
                             for r in range(1, pr.ik_restarts)]
-            pl, ok_p = pick(1, pose[p, b], starts)
+            pl, ok_p = pick(1, pose[p, b], starts, p, b)
             assert np.array_equal(pl, qp[p, b])
             n_acc += ok_g + ok_p
     assert n_acc > 0
@@ -795,7 +819,8 @@ def test_traj_init_candidate_rule(orc):
     P, B, W, seed = 3, prob.B, 16, 77
     qg = rng.uniform(-2, 2, (P, B, 7))
     qp = rng.uniform(-2, 2, (P, B, 7))
-    q = o.traj_init(qg, qp, W, seed=seed)
+    pose = o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.05))
+    q = o.traj_init(qg, qp, W, seed=seed, pose=pose)
     m = (W - 1) // 2
     qh = np.clip(prob.q_home, prob.lo, prob.hi)
     moved = 0
@@ -813,8 +838,10 @@ def test_traj_init_candidate_rule(orc):
                     u += list((raw >> np.uint64(40)).astype(np.float64) / 2.0**24)
                 qc = np.clip(0.5 * (qa + qb) + pr.mid_noise * (2 * np.array(u[:7]) - 1), prob.lo, prob.hi)
                 cands.append(qc)
-                scores.append(_np_arm_pen(o, prob, qc) + _np_arm_pen(o, prob, 0.5 * (qa + qc)) +
-                              _np_arm_pen(o, prob, 0.5 * (qc + qb)))
+                kind = 2 + s % 2
+                scores.append(_np_clutter(o, prob, qc, pose[p], b, kind) +
+                              _np_clutter(o, prob, 0.5 * (qa + qc), pose[p], b, kind) +
+                              _np_clutter(o, prob, 0.5 * (qc + qb), pose[p], b, kind))
             best = int(np.argmin(scores))
             assert np.array_equal(q[p, s, m], cands[best]), (p, s)
             moved += best != 0
