@@ -272,17 +272,19 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
         bool ov = false;
         if (ol < P.O) {
             const float4 bl = ldc(P.box, 4 * ol + 2), bh = ldc(P.box, 4 * ol + 3);
-            ov = bl.x <= hi0 && bh.x >= lo0 && bl.y <= hi1 && bh.y >= lo1 && bl.z <= hi2 && bh.z >= lo2;
+            ov = (bl.x <= hi0) & (bh.x >= lo0) & (bl.y <= hi1) & (bh.y >= lo1) & (bl.z <= hi2) & (bh.z >= lo2);
         }
         unsigned long long m = __ballot(ov);
         while (m) {
             const int o = base + __builtin_ctzll(m);
             m &= m - 1;
-            // lane pretest: the lane's own bounds against the obstacle
+            // lane pretest: the lane's own bounds against the obstacle (bitwise &, so the
+            // compares stay branch-free and combine as lane masks)
             const float4 bl = ldc(P.box, 4 * o + 2), bh = ldc(P.box, 4 * o + 3);
-            const bool lp = lb.lo0 <= bh.x && lb.hi0 >= bl.x && lb.lo1 <= bh.y && lb.hi1 >= bl.y &&
-                            lb.lo2 <= bh.z && lb.hi2 >= bl.z;
-            if (!__ballot(lp)) continue;
+            const unsigned long long lpm =
+                __ballot((lb.lo0 <= bh.x) & (lb.hi0 >= bl.x) & (lb.lo1 <= bh.y) & (lb.hi1 >= bl.y) &
+                         (lb.lo2 <= bh.z) & (lb.hi2 >= bl.z));
+            if (!lpm) continue;
             const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
             unsigned long long hm[CH], any = 0;
 #pragma unroll
@@ -290,7 +292,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
                 const float ux = fabsf(cx[i] - bc.x) - be.x;
                 const float uy = fabsf(cy[i] - bc.y) - be.y;
                 const float uz = fabsf(cz[i] - bc.z) - be.z;
-                hm[i] = __ballot(lp && fmaxf(fmaxf(ux, uy), uz) < r[i]);
+                hm[i] = __ballot(fmaxf(fmaxf(ux, uy), uz) < r[i]) & lpm;
                 any |= hm[i];
             }
             if (!any) continue;
@@ -326,16 +328,17 @@ __device__ __forceinline__ void collide_blocks(const KProb &P, int phase, float 
         const float tx = pp[0], ty = pp[1], tz = pp[2], cs = pp[4], sn = pp[5], ext = pp[6];
         // lane pretest against the block's axis-aligned bounds (xy half extent of the
         // yawed square in pp[6])
-        const bool vis = act && (bb != b || own_visible) && tx - ext <= lb.hi0 && tx + ext >= lb.lo0 &&
-                         ty - ext <= lb.hi1 && ty + ext >= lb.lo1 && tz - half <= lb.hi2 && tz + half >= lb.lo2;
-        if (!__ballot(vis)) continue;
+        const bool vis = act & (bb != b || own_visible) & (tx - ext <= lb.hi0) & (tx + ext >= lb.lo0) &
+                         (ty - ext <= lb.hi1) & (ty + ext >= lb.lo1) & (tz - half <= lb.hi2) & (tz + half >= lb.lo2);
+        const unsigned long long vm = __ballot(vis);
+        if (!vm) continue;
         unsigned long long hm[CH], any = 0;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const float dx = cx[i] - tx, dy = cy[i] - ty, dz = cz[i] - tz;
             const float lx = cs * dx + sn * dy, ly = cs * dy - sn * dx;
             const float ux = fabsf(lx) - half, uy = fabsf(ly) - half, uz = fabsf(dz) - half;
-            hm[i] = __ballot(vis && fmaxf(fmaxf(ux, uy), uz) < r[i]);
+            hm[i] = __ballot(fmaxf(fmaxf(ux, uy), uz) < r[i]) & vm;
             any |= hm[i];
         }
         if (!any) continue;
