@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 LIN, QUAD = 0, 1
-MODE_TOWER, MODE_FIXED = 0, 1
+MODE_TOWER, MODE_FIXED, MODE_PACK = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -41,7 +41,9 @@ class _Prob(ctypes.Structure):
                 ("sph_link", ctypes.c_void_p), ("sph_c", ctypes.c_void_p), ("sph_r", ctypes.c_void_p),
                 ("boxes", ctypes.c_void_p), ("h", ctypes.c_double), ("block_margin", ctypes.c_double),
                 ("block_init", ctypes.c_void_p), ("goal", ctypes.c_void_p), ("grasp", ctypes.c_void_p),
-                ("table", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+                ("table", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("pack_cells", ctypes.c_void_p), ("pack_off", ctypes.c_void_p),
+                ("sample_yaw_steps", ctypes.c_int)]
 
 
 _lib = None
@@ -61,6 +63,8 @@ def lib():
         L.or_box_sdf.restype = d
         L.or_obb_sdf.argtypes = [vp, vp, d, vp, vp]
         L.or_obb_sdf.restype = d
+        L.or_square_pen.argtypes = [vp, d, vp, d, d, vp]
+        L.or_square_pen.restype = d
         L.or_place_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp]
         L.or_traj_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_schedule.argtypes = [i, i, d, d, vp, vp]
@@ -102,6 +106,9 @@ class Oracle:
             "boxes": _f64(prob.boxes).reshape(-1, 6) if prob.O else np.zeros((1, 6)),
             "block_init": _f64(prob.block_init), "goal": _f64(prob.goal), "grasp": _f64(prob.grasp),
             "table": _f64(prob.table), "w": _f64(params.weights()),
+            "pack_cells": (np.ascontiguousarray(prob.pack_cells, dtype=np.int32)
+                           if getattr(prob, "pack_cells", None) is not None else None),
+            "pack_off": (_f64(prob.pack_off) if getattr(prob, "pack_off", None) is not None else None),
         }
         k = self._keep
         self.c = _Prob(prob.S, prob.O, prob.B, prob.mode, _ptr(k["dh"]).value, _ptr(k["lo"]).value,
@@ -109,7 +116,10 @@ class Oracle:
                        _ptr(k["sph_link"]).value, _ptr(k["sph_c"]).value, _ptr(k["sph_r"]).value,
                        _ptr(k["boxes"]).value, prob.h, prob.block_margin, _ptr(k["block_init"]).value,
                        _ptr(k["goal"]).value, _ptr(k["grasp"]).value, _ptr(k["table"]).value,
-                       _ptr(k["w"]).value)
+                       _ptr(k["w"]).value,
+                       _ptr(k["pack_cells"]).value if k["pack_cells"] is not None else None,
+                       _ptr(k["pack_off"]).value if k["pack_off"] is not None else None,
+                       int(getattr(prob, "sample_yaw_steps", 0)))
         self.ref = ctypes.byref(self.c)
 
     # -- geometry -------------------------------------------------------------------------
@@ -120,6 +130,15 @@ class Oracle:
         return out
 
     # -- costs ----------------------------------------------------------------------------
+    @staticmethod
+    def square_pen(ca, tha, cb, thb, s):
+        """Penetration depth of two squares of half edge s (separating axis theorem) and its
+        gradient d/d(ca_x, ca_y, tha, cb_x, cb_y, thb), plus the kink margin."""
+        ca, cb = _f64(ca), _f64(cb)
+        g = np.zeros(7)
+        pen = lib().or_square_pen(_ptr(ca), float(tha), _ptr(cb), float(thb), float(s), _ptr(g))
+        return pen, g[:6], g[6]
+
     def place_cost(self, x, phase=LIN, grad=True, dim=None):
         x = _f64(x)
         N, B, D = x.shape

@@ -237,6 +237,7 @@ static double pair_kink(double r, double sdf, double feat)
 
 static double zstar(const or_problem *pb, int i)
 {
+    if (pb->mode == 2) return 0.5 * pb->h; /* packing: every piece rests on the table */
     return pb->mode == 0 ? (i + 0.5) * pb->h : pb->goal[4 * i + 2];
 }
 
@@ -248,6 +249,177 @@ static void block_sphere(double h, int k, double *sb)
     sb[0] = (k & 1) ? qd : -qd;
     sb[1] = (k & 2) ? qd : -qd;
     sb[2] = (k & 4) ? qd : -qd;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Packing geometry (Appendix A, Tetris problem).  A piece is a union of square cells of
+ * edge h that share the piece's yaw; penetration depths are those of the squares.
+ * ------------------------------------------------------------------------------------ */
+
+/* Penetration depth of two squares of half edge s (centres ca, cb, yaws tha, thb) by the
+ * separating axis theorem: along each of the four edge normals n (ua, va of square a, ub,
+ * vb of square b) the two projections overlap by
+ *     s (|ua.n| + |va.n|) + s (|ub.n| + |vb.n|) - |(ca - cb).n|,
+ * and the depth (minimum translation distance) is the smallest of the four, or 0 when one
+ * of them is <= 0 (a separating axis).  g, when not NULL, receives
+ * d depth / d (ca_x, ca_y, tha, cb_x, cb_y, thb) for the axis of the smallest overlap
+ * (the first of ua, va, ub, vb on ties) and, in g[6], the distance of the configuration
+ * from a gradient switch: the gap to the second-smallest overlap, the depth itself,
+ * the projection of ca - cb on the chosen axis, and |cos|, |sin| of the relative yaw. */
+double or_square_pen(const double *ca, double tha, const double *cb, double thb, double s, double *g)
+{
+    const double ua[2] = {cos(tha), sin(tha)}, va[2] = {-sin(tha), cos(tha)};
+    const double ub[2] = {cos(thb), sin(thb)}, vb[2] = {-sin(thb), cos(thb)};
+    const double d[2] = {ca[0] - cb[0], ca[1] - cb[1]};
+    const double *axis[4] = {ua, va, ub, vb};
+    /* derivative of each axis by tha and by thb: ua' = va, va' = -ua (same for b) */
+    const double zero[2] = {0.0, 0.0}, mua[2] = {-ua[0], -ua[1]}, mub[2] = {-ub[0], -ub[1]};
+    const double *dax[4] = {va, mua, zero, zero}, *dbx[4] = {zero, zero, vb, mub};
+    double ov[4], gov[4][6];
+    for (int k = 0; k < 4; ++k) {
+        const double *n = axis[k], *na = dax[k], *nb = dbx[k];
+        double pu = ua[0] * n[0] + ua[1] * n[1], pv = va[0] * n[0] + va[1] * n[1];
+        double qu = ub[0] * n[0] + ub[1] * n[1], qv = vb[0] * n[0] + vb[1] * n[1];
+        double dist = d[0] * n[0] + d[1] * n[1];
+        ov[k] = s * (fabs(pu) + fabs(pv) + fabs(qu) + fabs(qv)) - fabs(dist);
+        /* derivatives of the projections by tha and thb */
+        double pu_a = va[0] * n[0] + va[1] * n[1] + ua[0] * na[0] + ua[1] * na[1];
+        double pv_a = -(ua[0] * n[0] + ua[1] * n[1]) + va[0] * na[0] + va[1] * na[1];
+        double qu_a = ub[0] * na[0] + ub[1] * na[1], qv_a = vb[0] * na[0] + vb[1] * na[1];
+        double pu_b = ua[0] * nb[0] + ua[1] * nb[1], pv_b = va[0] * nb[0] + va[1] * nb[1];
+        double qu_b = vb[0] * n[0] + vb[1] * n[1] + ub[0] * nb[0] + ub[1] * nb[1];
+        double qv_b = -(ub[0] * n[0] + ub[1] * n[1]) + vb[0] * nb[0] + vb[1] * nb[1];
+        double sd = sgn(dist);
+        gov[k][0] = -sd * n[0];
+        gov[k][1] = -sd * n[1];
+        gov[k][2] = s * (sgn(pu) * pu_a + sgn(pv) * pv_a + sgn(qu) * qu_a + sgn(qv) * qv_a) -
+                    sd * (d[0] * na[0] + d[1] * na[1]);
+        gov[k][3] = sd * n[0];
+        gov[k][4] = sd * n[1];
+        gov[k][5] = s * (sgn(pu) * pu_b + sgn(pv) * pv_b + sgn(qu) * qu_b + sgn(qv) * qv_b) -
+                    sd * (d[0] * nb[0] + d[1] * nb[1]);
+    }
+    int best = 0;
+    for (int k = 1; k < 4; ++k)
+        if (ov[k] < ov[best]) best = k;
+    double pen = ov[best] > 0.0 ? ov[best] : 0.0;
+    if (g) {
+        for (int c = 0; c < 6; ++c) g[c] = pen > 0.0 ? gov[best][c] : 0.0;
+        double gap = INFINITY;
+        for (int k = 0; k < 4; ++k)
+            if (k != best) gap = dmin(gap, ov[k] - ov[best]);
+        double dist = d[0] * axis[best][0] + d[1] * axis[best][1];
+        double cr = ua[0] * ub[0] + ua[1] * ub[1], sr = ua[0] * ub[1] - ua[1] * ub[0];
+        double kink = fabs(ov[best]);
+        if (ov[best] > 0.0) kink = dmin(kink, dmin(gap, dmin(fabs(dist), dmin(fabs(cr), fabs(sr)))));
+        g[6] = kink;
+    }
+    return pen;
+}
+
+/* Depth of a square (centre c, yaw th, half edge s) past a wall line with inward unit
+ * normal m at offset b (the interior is m.p >= b): b - (m.c - s (|ua.m| + |va.m|)).
+ * gc, gth: derivatives by c and th; kink: distance from a gradient switch. */
+static double wall_depth(const double *c, double th, double s, const double *m, double b, double *gc, double *gth,
+                         double *kink)
+{
+    const double ua[2] = {cos(th), sin(th)}, va[2] = {-sin(th), cos(th)};
+    double pu = ua[0] * m[0] + ua[1] * m[1], pv = va[0] * m[0] + va[1] * m[1];
+    double dep = b - (c[0] * m[0] + c[1] * m[1]) + s * (fabs(pu) + fabs(pv));
+    gc[0] = -m[0];
+    gc[1] = -m[1];
+    *gth = s * (sgn(pu) * pv - sgn(pv) * pu);
+    *kink = fabs(dep);
+    if (dep > 0.0) *kink = dmin(*kink, dmin(fabs(pu), fabs(pv)));
+    return dep;
+}
+
+/* Packing placement cost of one particle (Appendix A):
+ *   C = sum_{i<j} Pen(piece i, piece j) + sum_i sum_{walls} Pen(piece i, wall) + height term
+ * Pen(piece, piece) = sum over the cell pairs of phi(square depth); Pen(piece, wall) = sum
+ * over the cells of phi(depth past the wall); the walls are the four sides of the
+ * placement region.  The 3-dof state keeps z at h/2, so the height term is zero; the
+ * 4-dof state adds w_height (z - h/2)^2 as for towers (the paper's |z - z*| read as the
+ * same squared residual).  Every term is weighted by w_coll. */
+static void pack_one(const or_problem *pb, int dim, int phase, const double *x, double *cost_out,
+                     double *viol_out, double *g, double *kink_out)
+{
+    const int B = pb->B;
+    const double s = 0.5 * pb->h, w_height = pb->w[1], w_coll = pb->w[2];
+    const double *T = pb->table;
+    const double wall_m[4][2] = {{1.0, 0.0}, {-1.0, 0.0}, {0.0, 1.0}, {0.0, -1.0}};
+    const double wall_b[4] = {T[0], -T[1], T[2], -T[3]};
+    double P[B][4], gP[B][4];
+    for (int i = 0; i < B; ++i) {
+        P[i][0] = x[i * dim + 0];
+        P[i][1] = x[i * dim + 1];
+        P[i][2] = dim == 4 ? x[i * dim + 2] : zstar(pb, i);
+        P[i][3] = x[i * dim + dim - 1];
+        for (int c = 0; c < 4; ++c) gP[i][c] = 0.0;
+    }
+    double cost = 0.0, viol = 0.0, kink = INFINITY;
+    /* cell centre of cell k of piece i and its derivative by the piece yaw */
+    double C[B][8][2], dC[B][8][2];
+    for (int i = 0; i < B; ++i) {
+        double c = cos(P[i][3]), sn = sin(P[i][3]);
+        for (int k = 0; k < pb->pack_cells[i]; ++k) {
+            const double *o = pb->pack_off + (i * 8 + k) * 2;
+            C[i][k][0] = P[i][0] + c * o[0] - sn * o[1];
+            C[i][k][1] = P[i][1] + sn * o[0] + c * o[1];
+            dC[i][k][0] = -sn * o[0] - c * o[1];
+            dC[i][k][1] = c * o[0] - sn * o[1];
+        }
+    }
+    for (int i = 0; i < B; ++i) {
+        for (int k = 0; k < pb->pack_cells[i]; ++k) {
+            for (int wl = 0; wl < 4; ++wl) {
+                double gc[2], gth, kk;
+                double dep = wall_depth(C[i][k], P[i][3], s, wall_m[wl], wall_b[wl], gc, &gth, &kk);
+                kink = dmin(kink, kk);
+                if (dep > 0.0) {
+                    cost += w_coll * phi(phase, dep);
+                    viol = dmax(viol, dep);
+                    double sc = w_coll * dphi(phase, dep);
+                    gP[i][0] += sc * gc[0];
+                    gP[i][1] += sc * gc[1];
+                    gP[i][3] += sc * (gc[0] * dC[i][k][0] + gc[1] * dC[i][k][1] + gth);
+                }
+            }
+            for (int j = i + 1; j < B; ++j)
+                for (int m = 0; m < pb->pack_cells[j]; ++m) {
+                    double gs[7];
+                    double pen = or_square_pen(C[i][k], P[i][3], C[j][m], P[j][3], s, gs);
+                    kink = dmin(kink, gs[6]);
+                    if (pen > 0.0) {
+                        cost += w_coll * phi(phase, pen);
+                        viol = dmax(viol, pen);
+                        double sc = w_coll * dphi(phase, pen);
+                        gP[i][0] += sc * gs[0];
+                        gP[i][1] += sc * gs[1];
+                        gP[i][3] += sc * (gs[0] * dC[i][k][0] + gs[1] * dC[i][k][1] + gs[2]);
+                        gP[j][0] += sc * gs[3];
+                        gP[j][1] += sc * gs[4];
+                        gP[j][3] += sc * (gs[3] * dC[j][m][0] + gs[4] * dC[j][m][1] + gs[5]);
+                    }
+                }
+        }
+    }
+    for (int i = 0; i < B; ++i) {
+        double e = P[i][2] - zstar(pb, i);
+        cost += w_height * e * e;
+        viol = dmax(viol, fabs(e));
+        gP[i][2] += 2.0 * w_height * e;
+    }
+    *cost_out = cost;
+    *viol_out = viol;
+    if (kink_out) *kink_out = kink;
+    if (g)
+        for (int i = 0; i < B; ++i) {
+            g[i * dim + 0] = gP[i][0];
+            g[i * dim + 1] = gP[i][1];
+            if (dim == 4) g[i * dim + 2] = gP[i][2];
+            g[i * dim + dim - 1] = gP[i][3];
+        }
 }
 
 /* ------------------------------------------------------------------------------------
@@ -381,8 +553,8 @@ void or_place_cost(const or_problem *pb, int dim, int phase, int N, const double
     const int B = pb->B;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int n = 0; n < N; ++n)
-        place_one(pb, dim, phase, x + (size_t)n * B * dim, cost + n, viol + n,
-                  grad ? grad + (size_t)n * B * dim : NULL, kink ? kink + n : NULL);
+        (pb->mode == 2 ? pack_one : place_one)(pb, dim, phase, x + (size_t)n * B * dim, cost + n, viol + n,
+                                               grad ? grad + (size_t)n * B * dim : NULL, kink ? kink + n : NULL);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -703,6 +875,13 @@ void or_sample(const or_problem *pb, int N, uint64_t seed, int round, double *x)
             s[0] = xl + (xh - xl) * u[0];
             s[1] = yl + (yh - yl) * u[1];
             s[2] = -OR_PI + 2.0 * OR_PI * u[2];
+            if (pb->sample_yaw_steps > 0) {
+                /* yaw on n directions: the integer j = floor(n u) from the 24-bit draw */
+                const int n_dir = pb->sample_yaw_steps;
+                const int64_t k24 = (int64_t)(u[2] * 16777216.0);
+                const int64_t j = (n_dir * k24) >> 24;
+                s[2] = -OR_PI + 2.0 * OR_PI / n_dir * (double)j;
+            }
         }
 }
 

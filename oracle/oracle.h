@@ -13,7 +13,7 @@
 #include <stdint.h>
 
 typedef struct {
-    int S, O, B, mode;              /* mode 0: tower, 1: fixed goals */
+    int S, O, B, mode;              /* mode 0: tower, 1: fixed goals, 2: packing */
     const double *dh;               /* [7][3] a, d, alpha */
     const double *lo, *hi;          /* [7] */
     double tool_d;
@@ -28,6 +28,9 @@ typedef struct {
     const double *grasp;            /* [3][4] G: block -> end effector */
     const double *table;            /* [4] */
     const double *w;                /* [9] stable height coll start tie arm block lim smooth */
+    const int32_t *pack_cells;      /* [B] cells per piece (mode 2: packing), else NULL */
+    const double *pack_off;         /* [B][8][2] cell centres in the piece frame */
+    int sample_yaw_steps;           /* stage-1 yaw samples: 0 uniform, n > 0 on n directions */
 } or_problem;
 
 enum { OR_LIN = 0, OR_QUAD = 1 };
@@ -36,6 +39,7 @@ void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
 void or_fk(const or_problem *pb, const double *q, double *frames /* [9][12] */);
 double or_box_sdf(const double *p, const double *box, double *grad);
 double or_obb_sdf(const double *p, const double *pose, double half, double *gp, double *gpose);
+double or_square_pen(const double *ca, double tha, const double *cb, double thb, double s, double *g);
 
 void or_place_cost(const or_problem *pb, int dim, int phase, int N, const double *x,
                    double *cost, double *viol, double *grad, double *kink);

@@ -39,6 +39,8 @@ REGION = (0.2, 0.55, -0.35, 0.35)        # placement region (the problem's bound
 
 MODE_TOWER = 0                           # block b goes to tower slot b (heights (b+1/2) h)
 MODE_FIXED = 1                           # block b goes to a given fixed pose
+MODE_PACK = 2                            # polyomino pieces packed into the region (stage 1 only)
+MAX_CELLS = 8                            # cells per packing piece
 
 # weight order shared by every consumer of Params.weights()
 WEIGHT_NAMES = ("stable", "height", "coll", "start", "tie", "arm", "block", "lim", "smooth")
@@ -62,6 +64,12 @@ class Problem:
     grasp: np.ndarray         # (3, 4) rigid transform G, block frame -> end-effector frame
     table: np.ndarray         # (4,) placement region x_lo, x_hi, y_lo, y_hi
     block_margin: float = 1e-3  # block collision spheres have radius h/4 - block_margin
+    # packing pieces (MODE_PACK): piece b is the union of pack_cells[b] square cells of edge
+    # h centred at pack_off[b, k] in the piece frame; the region is the packing box
+    pack_cells: np.ndarray = None   # (B,) int32, 1..MAX_CELLS
+    pack_off: np.ndarray = None     # (B, MAX_CELLS, 2) float64, unused rows zero
+    pack_solution: np.ndarray = None  # (B, 3) one exact packing (x, y, yaw), for tests
+    sample_yaw_steps: int = 0       # stage-1 yaw samples: 0 uniform, n > 0 on n directions
 
     @property
     def S(self) -> int:
@@ -120,6 +128,12 @@ class Params:
 
     def k_lin2(self, K: int) -> int:
         return int(round(self.lin_frac2 * K))
+
+
+# stage-1 step sizes of the packing workloads (the paper tunes them per problem): a
+# smaller quadratic step than the towers', chosen on seeds of the 5-piece box with the
+# oracle (7 of 8 solved within 8 rounds of 4096 samples, 512 kept)
+PACK_PARAMS = Params(eta1=0.005, alpha1=0.1)
 
 
 @dataclasses.dataclass
@@ -245,6 +259,82 @@ def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
                    table=np.array(REGION, dtype=np.float64))
 
 
+def _partition(rng: np.random.Generator, rows: int, cols: int, B: int) -> np.ndarray:
+    """Random partition of a rows x cols grid into B 4-connected pieces of near-equal size
+    (grown from random seed cells, one random frontier cell at a time; redrawn when a
+    piece gets boxed in).  Returns the owner index of every cell."""
+    n = rows * cols
+    sizes = [n // B + (1 if k < n % B else 0) for k in range(B)]
+    if max(sizes) > MAX_CELLS:
+        raise ValueError("pieces of more than %d cells" % MAX_CELLS)
+    for _ in range(10000):
+        owner = -np.ones((rows, cols), dtype=np.int64)
+        start = rng.choice(n, B, replace=False)
+        count = [1] * B
+        for k, c in enumerate(start):
+            owner[c // cols, c % cols] = k
+        stuck = False
+        while any(count[k] < sizes[k] for k in range(B)):
+            grow = []
+            for k in range(B):
+                if count[k] >= sizes[k]:
+                    continue
+                front = set()
+                for (r, c) in zip(*np.nonzero(owner == k)):
+                    for dr, dc in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                        rr, cc = r + dr, c + dc
+                        if 0 <= rr < rows and 0 <= cc < cols and owner[rr, cc] < 0:
+                            front.add((int(rr), int(cc)))
+                if front:
+                    grow.append((k, sorted(front)))
+            if not grow:
+                stuck = True
+                break
+            k, front = grow[int(rng.integers(len(grow)))]
+            r, c = front[int(rng.integers(len(front)))]
+            owner[r, c] = k
+            count[k] += 1
+        if not stuck:
+            return owner
+    raise ValueError("no partition found")
+
+
+def make_packing(seed: int, B: int, rows: int, cols: int, cell: float = 0.04) -> Problem:
+    """Draw one seeded packing problem (the paper's Tetris task, Sec. IV, with synthetic
+    pieces): the rows x cols box of square cells (edge `cell`) is cut into B connected
+    polyominoes that fill it without gaps, so every exact packing uses all of the space.
+    The robot part is drawn as for the towers (the packing cost does not use it).  Piece
+    frames sit at the centroid of their cells; initial poses are a row of spots outside
+    the box.  Stage-1 yaw samples are quarter turns: exact packings of square cells only
+    exist there."""
+    rng = np.random.default_rng([seed, B, rows, cols, 0x7E7A])
+    base = make_problem(seed, B=1, O=0, S=42, mode=MODE_TOWER, h=cell)
+    owner = _partition(rng, rows, cols, B)
+    xc = 0.5 * (REGION[0] + REGION[1])
+    x0, y0 = xc - 0.5 * cols * cell, -0.5 * rows * cell
+    n_cells = np.zeros(B, dtype=np.int32)
+    off = np.zeros((B, MAX_CELLS, 2))
+    sol = np.zeros((B, 3))
+    for k in range(B):
+        rr, cc = np.nonzero(owner == k)
+        cx = x0 + (cc + 0.5) * cell
+        cy = y0 + (rr + 0.5) * cell
+        ox, oy = float(cx.mean()), float(cy.mean())
+        n_cells[k] = len(cx)
+        off[k, : len(cx), 0] = cx - ox
+        off[k, : len(cx), 1] = cy - oy
+        sol[k] = [ox, oy, 0.0]
+    yaw = rng.uniform(-math.pi, math.pi, B)
+    block_init = np.array([[-0.3 + 0.6 * (k + 0.5) / B, -0.4, cell / 2, yaw[k]] for k in range(B)])
+    goal = np.zeros((B, 4))
+    goal[:, :] = math.nan
+    goal[:, 2] = cell / 2
+    region = np.array([x0, x0 + cols * cell, y0, y0 + rows * cell])
+    return dataclasses.replace(base, boxes=np.zeros((0, 6)), h=cell, block_init=block_init, mode=MODE_PACK,
+                               goal=goal, table=region, pack_cells=n_cells, pack_off=off, pack_solution=sol,
+                               sample_yaw_steps=4)
+
+
 _SEEDS_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
                            "reachable_seeds.txt")
 
@@ -261,6 +351,15 @@ def certified_seeds(name: str) -> list:
     raise KeyError(name)
 
 
+def instance_seeds(name: str) -> list:
+    """Scene seeds of a workload: the certified list for the tower workloads (their
+    instances depend on the robot reaching every block), seeds 0..99 for the packing
+    workloads (stage 1 only)."""
+    if name.startswith("tetris"):
+        return list(range(100))
+    return certified_seeds(name)
+
+
 # The five workloads.  C1..C3 are solve configurations, C4 is the differentiable-cost
 # batch, C5 is the serving mix (sizes drawn per request).
 def config(name: str, seed: int = 0):
@@ -274,6 +373,12 @@ def config(name: str, seed: int = 0):
     if name == "tower10":        # 10-block tower, 80 boxes, 20 x 32 waypoints, 48 spheres
         prob = make_problem(seed, B=10, O=80, S=48)
         return prob, Params(), SolveConfig(N1=16384, M=2048, W=32, K=300, seed=seed)
+    if name == "tetris5":        # 5 pieces of 4 cells packed into a 4 x 5 box (stage 1 only)
+        prob = make_packing(seed, B=5, rows=4, cols=5)
+        return prob, dataclasses.replace(PACK_PARAMS), SolveConfig(N1=4096, M=1024, W=32, K=0, seed=seed)
+    if name == "tetris8":        # 8 pieces of 4 cells packed into a 4 x 8 box (stage 1 only)
+        prob = make_packing(seed, B=8, rows=4, cols=8)
+        return prob, dataclasses.replace(PACK_PARAMS), SolveConfig(N1=16384, M=2048, W=32, K=0, seed=seed)
     raise KeyError(name)
 
 
@@ -329,4 +434,14 @@ def clustered_placements(rng: np.random.Generator, prob: Problem, N: int, spread
     x[..., 0] = cx + rng.normal(0, spread, size=(N, B))
     x[..., 1] = cy + rng.normal(0, spread, size=(N, B))
     x[..., 2] = rng.uniform(-math.pi, math.pi, size=(N, B))
+    return x
+
+
+def near_packing(rng: np.random.Generator, prob: Problem, N: int, spread: float = 0.004,
+                 yaw_spread: float = 0.05):
+    """Stage-1 states of a packing problem scattered around its exact packing (Gaussian
+    noise on x, y and yaw), so that the cell-cell and wall contacts are active and shallow."""
+    x = np.repeat(prob.pack_solution[None], N, axis=0).copy()
+    x[..., :2] += rng.normal(0, spread, size=(N, prob.B, 2))
+    x[..., 2] += rng.normal(0, yaw_spread, size=(N, prob.B))
     return x

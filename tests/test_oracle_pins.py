@@ -846,3 +846,158 @@ def test_traj_init_candidate_rule(orc):
             assert np.array_equal(q[p, s, m], cands[best]), (p, s)
             moved += best != 0
     assert moved > 0   # the rule does change some choices
+
+
+# ------------------------------------------------------------------- packing (Tetris)
+def _square_vertices(c, th, s):
+    u = np.array([math.cos(th), math.sin(th)])
+    v = np.array([-math.sin(th), math.cos(th)])
+    c = np.asarray(c, float)
+    return np.array([c + a * s * u + b * s * v for a in (-1, 1) for b in (-1, 1)])
+
+
+def _mtd_brute_force(ca, tha, cb, thb, s, n_dir=20000, n_fine=2001):
+    """Penetration depth of two convex sets as the smallest overlap of their projections
+    over all directions, from the vertices alone: a sweep of half a turn, then a fine
+    sweep of one coarse step either side of every coarse direction that could hold the
+    minimum (the overlap is Lipschitz in the angle with constant at most the largest
+    vertex distance from the origin, times two)."""
+    A, B = _square_vertices(ca, tha, s), _square_vertices(cb, thb, s)
+
+    def overlap(ang):
+        U = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+        pa, pb = A @ U.T, B @ U.T
+        return np.minimum(pa.max(0) - pb.min(0), pb.max(0) - pa.min(0))
+
+    step = math.pi / n_dir
+    ang = np.arange(n_dir) * step
+    ov = overlap(ang)
+    lip = 2.0 * float(np.abs(np.concatenate([A, B])).max()) * 2.0
+    best = float(ov.min())
+    for k in np.nonzero(ov <= best + lip * step)[0]:
+        best = min(best, float(overlap(np.linspace(ang[k] - step, ang[k] + step, n_fine)).min()))
+    return max(0.0, best)
+
+
+def test_square_pen_brute_force(orc):
+    """The separating-axis depth equals the minimum projection overlap over every
+    direction (the definition of penetration depth of convex sets), including 0 for
+    separated squares."""
+    rng = np.random.default_rng(31)
+    s = 0.02
+    n_pos = 0
+    for _ in range(300):
+        ca = rng.uniform(-0.03, 0.03, 2)
+        cb = rng.uniform(-0.03, 0.03, 2)
+        tha, thb = rng.uniform(-math.pi, math.pi, 2)
+        pen, _, _ = orc.Oracle.square_pen(ca, tha, cb, thb, s)
+        bf = _mtd_brute_force(ca, tha, cb, thb, s)
+        # the fine sweep lands within 1e-6 rad of the optimal direction
+        assert pen == pytest.approx(bf, abs=1e-7), (ca, tha, cb, thb)
+        n_pos += pen > 0
+    assert 50 < n_pos < 300
+
+
+def test_square_pen_closed_forms(orc):
+    s = 0.02
+    # face-face: axis-aligned squares overlapping by 0.003 in x and 0.01 in y
+    pen, g, _ = orc.Oracle.square_pen([0.0, 0.0], 0.0, [2 * s - 0.003, 2 * s - 0.01], 0.0, s)
+    assert pen == pytest.approx(0.003, abs=1e-15)
+    # b lies towards +x: moving a towards it deepens the overlap one for one
+    assert g[:2] == pytest.approx([1.0, 0.0]) and g[3:5] == pytest.approx([-1.0, 0.0])
+    # vertex into face: a quarter-turn-by-half (45 degree) square whose corner reaches
+    # into an axis-aligned square's face; the corner sits s*sqrt(2) from its centre
+    D = 0.045
+    pen, _, _ = orc.Oracle.square_pen([0.0, 0.0], 0.0, [D, 0.0], math.pi / 4, s)
+    assert pen == pytest.approx(s + s * math.sqrt(2) - D, abs=1e-15)
+    # separated (gap along x) and touching squares: no depth
+    assert orc.Oracle.square_pen([0, 0], 0.0, [2 * s + 1e-4, 0.0], 0.0, s)[0] == 0.0
+    assert orc.Oracle.square_pen([0, 0], 0.3, [0.1, 0.0], -0.2, s)[0] == 0.0
+    # symmetric in the two squares, invariant under a quarter turn of either
+    a = ([0.001, 0.002], 0.4, [0.02, -0.01], 1.1)
+    p0 = orc.Oracle.square_pen(a[0], a[1], a[2], a[3], s)[0]
+    assert orc.Oracle.square_pen(a[2], a[3], a[0], a[1], s)[0] == pytest.approx(p0, abs=1e-15)
+    assert orc.Oracle.square_pen(a[0], a[1] + math.pi / 2, a[2], a[3] - math.pi, s)[0] == pytest.approx(p0, abs=1e-15)
+
+
+def test_square_pen_grad_fd(orc):
+    rng = np.random.default_rng(32)
+    s, hstep = 0.02, 1e-7
+    checked = 0
+    for _ in range(200):
+        v = np.concatenate([rng.uniform(-0.02, 0.02, 2), rng.uniform(-math.pi, math.pi, 1),
+                            rng.uniform(-0.02, 0.02, 2), rng.uniform(-math.pi, math.pi, 1)])
+        pen, g, kink = orc.Oracle.square_pen(v[0:2], v[2], v[3:5], v[5], s)
+        if pen <= 0 or kink < 100 * hstep:
+            continue
+        for c in range(6):
+            vp, vm = v.copy(), v.copy()
+            vp[c] += hstep
+            vm[c] -= hstep
+            fd = (orc.Oracle.square_pen(vp[0:2], vp[2], vp[3:5], vp[5], s)[0]
+                  - orc.Oracle.square_pen(vm[0:2], vm[2], vm[3:5], vm[5], s)[0]) / (2 * hstep)
+            assert fd == pytest.approx(g[c], abs=1e-6), (v, c)
+        checked += 1
+    assert checked > 50
+
+
+@pytest.mark.parametrize("name", ["tetris5", "tetris8"])
+def test_pack_exact_packing_is_free(orc, name):
+    """The generator's packing fills the box without gaps: zero cost up to rounding, and
+    any piece pushed by 1 mm into the box's interior side costs exactly 1 mm per cell
+    edge it drives into a neighbour or wall (linear phase)."""
+    for seed in range(5):
+        prob, pr, _ = synth.config(name, seed)
+        o = orc.Oracle(prob, pr)
+        x = prob.pack_solution[None].copy()
+        c, v, _, _ = o.place_cost(x, grad=False)
+        assert c[0] < 1e-12 and v[0] < 1e-12
+        # shifting the whole packing sideways pushes every cell of the leftmost column
+        # 1 mm past the left wall and leaves every cell-cell contact at depth 0
+        xs = x.copy()
+        xs[0, :, 0] -= 0.001
+        c, v, _, _ = o.place_cost(xs, grad=False)
+        assert v[0] == pytest.approx(0.001, abs=1e-12)
+        rows = round((prob.table[3] - prob.table[2]) / prob.h)
+        assert c[0] == pytest.approx(rows * 0.001 * pr.w_coll, abs=1e-12)
+
+
+def test_pack_wall_closed_form(orc):
+    """A single cell turned by 45 degrees: its corner sits s*sqrt(2) from the centre, so
+    at distance D from the left wall it reaches s*sqrt(2) - D past it."""
+    prob, pr, _ = synth.config("tetris5", 0)
+    one = synth.dataclasses.replace(prob, block_init=prob.block_init[:1], goal=prob.goal[:1],
+                                    pack_cells=np.array([1], np.int32), pack_off=np.zeros((1, 8, 2)),
+                                    pack_solution=None)
+    o = orc.Oracle(one, pr)
+    s = prob.h / 2
+    D = 0.02
+    x = np.array([[[prob.table[0] + D, 0.5 * (prob.table[2] + prob.table[3]), math.pi / 4]]])
+    c, v, _, _ = o.place_cost(x, grad=False)
+    assert v[0] == pytest.approx(s * math.sqrt(2) - D, abs=1e-15)
+    assert c[0] == pytest.approx(pr.w_coll * (s * math.sqrt(2) - D), abs=1e-15)
+
+
+@pytest.mark.parametrize("name", ["tetris5", "tetris8"])
+def test_pack_grad_fd(orc, name):
+    rng = np.random.default_rng(33)
+    prob, pr, _ = synth.config(name, 2)
+    o = orc.Oracle(prob, pr)
+    hstep = 1e-7
+    checked = 0
+    for x in (synth.near_packing(rng, prob, 6), synth.random_placements(rng, prob, 4)):
+        for phase in (orc.LIN, orc.QUAD):
+            c, v, g, kink = o.place_cost(x, phase=phase)
+            for n in range(x.shape[0]):
+                if kink[n] < 100 * hstep:
+                    continue
+                for i in range(prob.B):
+                    for k in range(3):
+                        xp, xm = x[n:n + 1].copy(), x[n:n + 1].copy()
+                        xp[0, i, k] += hstep
+                        xm[0, i, k] -= hstep
+                        fd = (o.place_cost(xp, phase, grad=False)[0][0]
+                              - o.place_cost(xm, phase, grad=False)[0][0]) / (2 * hstep)
+                        assert fd == pytest.approx(g[n, i, k], abs=2e-6, rel=1e-6), (phase, n, i, k)
+                        checked += 1
+    assert checked > 0
