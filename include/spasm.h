@@ -51,6 +51,7 @@ extern "C" {
 #define SPASM_PHASE_QUAD 1     /* squared residuals (quadratic refinement) */
 #define SPASM_MODE_TOWER 0     /* block b goes to tower slot b, centre height (b + 1/2) h */
 #define SPASM_MODE_FIXED 1     /* block b goes to goal[b] */
+#define SPASM_MODE_PACK 2      /* polyomino pieces packed into the region (stage 1 only) */
 
 typedef struct spasm_problem_s *spasm_problem;
 
@@ -64,16 +65,27 @@ typedef struct {
 } spasm_chain_desc;
 
 /* Blocks and action skeleton: block b is picked from block_init[b] and placed either on
- * the tower (slot b) or at goal[b]; blocks are moved in index order. */
+ * the tower (slot b) or at goal[b]; blocks are moved in index order.
+ * Packing (SPASM_MODE_PACK, the Tetris problem of Sec. IV and Appendix A): block b is a
+ * piece made of pack_cells[b] square cells of edge block_edge centred at pack_off[b][k]
+ * in the piece frame; the pieces are packed into the region, whose four sides are the
+ * walls.  Packing problems support the stage-1 entry points only (sample, placement
+ * cost, stage-1 optimize, selection, order, place_round); the stage-2 entry points
+ * return SPASM_EUNSUPPORTED for them. */
 typedef struct {
     int32_t n_blocks;         /* B >= 1 */
-    int32_t mode;             /* SPASM_MODE_TOWER or SPASM_MODE_FIXED */
+    int32_t mode;             /* SPASM_MODE_TOWER, SPASM_MODE_FIXED or SPASM_MODE_PACK */
     double block_edge;        /* h: cube edge */
     double block_margin;      /* block collision spheres have radius h/4 - margin */
     const double *block_init; /* host [B][4] x, y, z, yaw */
     const double *goal;       /* host [B][4] (SPASM_MODE_FIXED), ignored for towers */
     double grasp[3][4];       /* G: block frame -> end-effector frame, [R | t] */
     double region[4];         /* placement bounding box x_lo, x_hi, y_lo, y_hi */
+    const int32_t *pack_cells; /* host [B] cells per piece, 1..8 (SPASM_MODE_PACK), else NULL */
+    const double *pack_off;    /* host [B][8][2] cell centres in the piece frame (rows k >=
+                                * pack_cells[b] ignored); cells of one piece must not overlap */
+    int32_t sample_yaw_steps;  /* stage-1 yaw samples: 0 = uniform in [-pi, pi); n in 1..64 =
+                                * the n directions -pi + 2 pi j / n */
 } spasm_skeleton_desc;
 
 /* Weights and schedules.  Stage 1 (Alg. 1): k_lin1 linear steps with
@@ -128,15 +140,19 @@ int spasm_problem_blocks(spasm_problem prob);
 
 /* --- stage 1 --------------------------------------------------------------------------
  * Alg. 1 SampleUniform: N placements, x and y uniform over the region shrunk by h/2, yaw
- * uniform in [-pi, pi).  Philox4x64-10 with key (seed, 0) and counter (particle, block,
- * round, 1); uniforms are the top 24 bits.  d_x: [N][B][3]. */
+ * uniform in [-pi, pi) (or, with sample_yaw_steps = n > 0, -pi + (2 pi / n) floor(n u)).
+ * Philox4x64-10 with key (seed, 0) and counter (particle, block, round, 1); uniforms are
+ * the top 24 bits.  d_x: [N][B][3]. */
 int spasm_sample(spasm_problem prob, int32_t N, uint64_t seed, int32_t round, float *d_x,
                  void *stream);
 
 /* --- costs ----------------------------------------------------------------------------
  * Cost, violation and gradient of a batch (Appendix B).
  * stage SPASM_STAGE_PLACE: d_x [P][B][3] placements; C_placement with z at the slot
- *   heights; d_gx [P][B][3]; W and d_pose unused.
+ *   heights; d_gx [P][B][3]; W and d_pose unused.  Packing problems (Appendix A): the sum
+ *   over cell pairs of different pieces of the squares' penetration depth (separating
+ *   axis theorem) plus the sum over cells of the depth past each wall, weighted by
+ *   w_coll and passed through the phase's penalty (identity or square).
  * stage SPASM_STAGE_TRAJ: d_x = q [P][2B][W][7], d_pose [P][B][4];
  *   C_trajopt = C_placement(pose) + w_start C_start + w_tie C_tie + w_arm (C_arm + arm vs
  *   blocks) + w_block C_block + w_lim C_lim + w_smooth C_smooth.  d_gx [P][2B][W][7] is the

@@ -80,8 +80,17 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     if (n_obs > 0 && !boxes) return fail(SPASM_EINVAL, "obstacle array is NULL");
     const int B = skel->n_blocks;
     if (B < 1 || B > MAX_B) return fail(SPASM_EUNSUPPORTED, "n_blocks=%d outside 1..%d", B, MAX_B);
-    if (skel->mode != SPASM_MODE_TOWER && skel->mode != SPASM_MODE_FIXED)
+    if (skel->mode != SPASM_MODE_TOWER && skel->mode != SPASM_MODE_FIXED && skel->mode != SPASM_MODE_PACK)
         return fail(SPASM_EINVAL, "unknown skeleton mode %d", skel->mode);
+    if (skel->sample_yaw_steps < 0 || skel->sample_yaw_steps > 64)
+        return fail(SPASM_EINVAL, "sample_yaw_steps=%d outside 0..64", skel->sample_yaw_steps);
+    if (skel->mode == SPASM_MODE_PACK) {
+        if (!skel->pack_cells || !skel->pack_off) return fail(SPASM_EINVAL, "packing needs pack_cells and pack_off");
+        for (int b = 0; b < B; ++b)
+            if (skel->pack_cells[b] < 1 || skel->pack_cells[b] > 8)
+                return fail(SPASM_EINVAL, "piece %d: %d cells outside 1..8", b, skel->pack_cells[b]);
+        if (!finite_all(skel->pack_off, (size_t)B * 16)) return fail(SPASM_EINVAL, "non-finite cell offset");
+    }
     if (!skel->block_init) return fail(SPASM_EINVAL, "block_init is NULL");
     if (skel->mode == SPASM_MODE_FIXED && !skel->goal) return fail(SPASM_EINVAL, "fixed goals need goal poses");
     if (!finite_all(&chain->dh[0][0], 21) || !finite_all(chain->lo, 7) || !finite_all(chain->hi, 7) ||
@@ -182,8 +191,15 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
             dst[8 * b + 5] = (float)std::sin(src[4 * b + 3]);
         }
     };
-    std::vector<float> init, goal;
+    std::vector<float> init, goal, cells((size_t)B * 8 * 4, 0.f);
     pack_poses(skel->block_init, init);
+    if (skel->mode == SPASM_MODE_PACK)  // [B][8] (ox, oy, 1 for a cell of the piece, 0)
+        for (int b = 0; b < B; ++b)
+            for (int k = 0; k < skel->pack_cells[b]; ++k) {
+                cells[(b * 8 + k) * 4 + 0] = (float)skel->pack_off[(b * 8 + k) * 2 + 0];
+                cells[(b * 8 + k) * 4 + 1] = (float)skel->pack_off[(b * 8 + k) * 2 + 1];
+                cells[(b * 8 + k) * 4 + 2] = 1.f;
+            }
     if (skel->mode == SPASM_MODE_FIXED)
         pack_poses(skel->goal, goal);
     else
@@ -193,12 +209,14 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     const size_t off_box = align256((off_sph + n_sphf) * 4) / 4, n_boxf = box.size();
     const size_t off_init = align256((off_box + n_boxf) * 4) / 4;
     const size_t off_goal = align256((off_init + init.size()) * 4) / 4;
-    const size_t total = align256((off_goal + goal.size()) * 4);
+    const size_t off_cells = align256((off_goal + goal.size()) * 4) / 4;
+    const size_t total = align256((off_cells + cells.size()) * 4);
     std::vector<float> host(total / 4, 0.f);
     std::copy(sph.begin(), sph.end(), host.begin() + off_sph);
     std::copy(box.begin(), box.end(), host.begin() + off_box);
     std::copy(init.begin(), init.end(), host.begin() + off_init);
     std::copy(goal.begin(), goal.end(), host.begin() + off_goal);
+    std::copy(cells.begin(), cells.end(), host.begin() + off_cells);
 
     auto *pb = new spasm_problem_s();
     if (hipGetDevice(&pb->device) != hipSuccess) {
@@ -221,6 +239,9 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.box = (const float4 *)(base + off_box);
     K.blk_init = (const float4 *)(base + off_init);
     K.goal = (const float4 *)(base + off_goal);
+    K.cells = (const float4 *)(base + off_cells);
+    K.yaw_steps = skel->sample_yaw_steps;
+    for (int c = 0; c < 4; ++c) K.wall[c] = (float)skel->region[c];
     K.B = B;
     K.S = link_start[7];
     K.O = n_obs;
@@ -294,7 +315,11 @@ extern "C" void spasm_problem_destroy(spasm_problem prob)
 
 extern "C" int spasm_problem_blocks(spasm_problem prob) { return prob ? prob->kp.B : 0; }
 
-static int check_traj_shape(spasm_problem prob, int P, int W) { return spasm::check_traj_shape(prob->kp.B, P, W); }
+static int check_traj_shape(spasm_problem prob, int P, int W)
+{
+    if (prob->kp.mode == SPASM_MODE_PACK) return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only");
+    return spasm::check_traj_shape(prob->kp.B, P, W);
+}
 
 extern "C" int spasm_sample(spasm_problem prob, int32_t N, uint64_t seed, int32_t round, float *d_x, void *stream)
 {
@@ -514,6 +539,7 @@ extern "C" int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, con
                                 int32_t iters, void *stream)
 {
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (prob->kp.mode == SPASM_MODE_PACK) return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only");
     if (kind != 0 && kind != 1) return fail(SPASM_EINVAL, "kind must be 0 (grasp) or 1 (place)");
     if (n < 1 || iters < 0 || !d_target || !d_q) return fail(SPASM_EINVAL, "bad size or NULL buffer");
     SPASM_HIP(launch_ik_iterate(prob->kp, kind, n, d_target, d_q, iters, (hipStream_t)stream));
@@ -524,6 +550,7 @@ extern "C" int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose,
                              float *d_qgrasp, float *d_qplace, void *stream)
 {
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (prob->kp.mode == SPASM_MODE_PACK) return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only");
     if (P < 1 || iters < 0 || !d_pose || !d_qgrasp || !d_qplace) return fail(SPASM_EINVAL, "bad size or NULL buffer");
     SPASM_HIP(launch_ik_lift(prob->kp, P, d_pose, seed, iters, d_qgrasp, d_qplace, (hipStream_t)stream));
     return SPASM_OK;
@@ -599,6 +626,8 @@ SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c)
 int check_cfg(spasm_problem prob, const spasm_solve_config *cfg)
 {
     if (!prob || !cfg) return fail(SPASM_EINVAL, "problem and config are required");
+    if (prob->kp.mode == SPASM_MODE_PACK)
+        return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only (place_round)");
     if (cfg->M < 1 || cfg->M > MAX_SORT) return fail(SPASM_EUNSUPPORTED, "M=%d outside 1..%d", cfg->M, MAX_SORT);
     if (prob->kp.mode == SPASM_MODE_TOWER) {
         if (cfg->N1 < cfg->M || cfg->N1 > MAX_SORT)

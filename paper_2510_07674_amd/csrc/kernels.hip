@@ -33,11 +33,12 @@ __device__ __forceinline__ float4 ldc(const float4 *p, int i)
 __device__ __forceinline__ float phi(int phase, float d) { return phase ? d * d : d; }
 __device__ __forceinline__ float dphi(int phase, float d) { return phase ? 2.f * d : 1.f; }
 
-// Target centre height of block b (tower slot or fixed goal).  Computed, not read from
-// an array in the kernel argument: a per-lane index into the by-value argument would
-// force the whole argument into per-lane scratch memory.
+// Target centre height of block b (tower slot, fixed goal, or on the table for packing
+// pieces).  Computed, not read from an array in the kernel argument: a per-lane index
+// into the by-value argument would force the whole argument into per-lane scratch memory.
 __device__ __forceinline__ float zstar(const KProb &P, int b)
 {
+    if (P.mode == SPASM_MODE_PACK) return 0.5f * P.h;
     return P.mode == 0 ? ((float)b + 0.5f) * P.h : ldc(P.goal, 2 * b).z;
 }
 
@@ -522,6 +523,107 @@ __device__ __forceinline__ void place_lane(const KProb &P, int phase, int i, int
     }
 }
 
+// Packing placement cost (Appendix A, Tetris problem) of cell k of piece i: the cell
+// against the four walls of the region and against every cell of the other pieces.
+// Cells are squares of half edge s that share their piece's yaw.  For two of them with
+// relative yaw D and centre offset d, the projected half extents along any of the four
+// edge normals n sum to s (1 + |cos D| + |sin D|), so the separating-axis depth is that
+// sum minus the largest |d.n|.  A pair's cost is taken by the lane of the lower-numbered
+// piece; every lane adds the gradient of all of its pairs with respect to its own piece,
+// so no lane writes another's gradient.  Lanes past the piece's last cell only hold the
+// height term (lane 0).
+template <bool GRAD>
+__device__ __forceinline__ void pack_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost,
+                                          float &viol, float (&g)[4])
+{
+    const float w = P.w[W_COLL], s = P.half;
+    if (k == 0) {  // height: zero while z stays on the table
+        const float w_h = P.w[W_HEIGHT];
+        const float e = st[i * 8 + 2] - zstar(P, i);
+        cost += w_h * e * e;
+        viol = fmaxf(viol, fabsf(e));
+        if (GRAD) g[2] += 2.f * w_h * e;
+    }
+    const float4 ck = ldc(P.cells, 8 * i + k);
+    if (ck.z == 0.f) return;
+    const float xi = st[i * 8 + 0], yi = st[i * 8 + 1], ci = st[i * 8 + 4], si = st[i * 8 + 5];
+    const float ax = xi + ci * ck.x - si * ck.y, ay = yi + si * ck.x + ci * ck.y;
+    const float dax = -si * ck.x - ci * ck.y, day = ci * ck.x - si * ck.y;  // d(ax, ay) / d yaw_i
+    // walls: the cell reaches e = s (|cos| + |sin|) from its centre along x and along y
+    const float e = s * (fabsf(ci) + fabsf(si));
+    const float de = s * (sgnf(si) * ci - sgnf(ci) * si);  // d e / d yaw_i
+    const float wd[4] = {P.wall[0] - (ax - e), (ax + e) - P.wall[1], P.wall[2] - (ay - e), (ay + e) - P.wall[3]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (wd[q] > 0.f) {
+            cost += w * phi(phase, wd[q]);
+            viol = fmaxf(viol, wd[q]);
+            if (GRAD) {
+                const float sc = w * dphi(phase, wd[q]);
+                const float sgn = (q & 1) ? 1.f : -1.f;  // inward side: -1 for x_lo / y_lo
+                if (q < 2) {
+                    g[0] += sc * sgn;
+                    g[3] += sc * (sgn * dax + de);
+                } else {
+                    g[1] += sc * sgn;
+                    g[3] += sc * (sgn * day + de);
+                }
+            }
+        }
+    }
+    for (int j = 0; j < P.B; ++j) {
+        if (j == i) continue;
+        const float xj = st[j * 8 + 0], yj = st[j * 8 + 1], cj = st[j * 8 + 4], sj = st[j * 8 + 5];
+        const float cD = cj * ci + sj * si, sD = sj * ci - cj * si;  // cos, sin of yaw_j - yaw_i
+        const float R = s * (1.f + fabsf(cD) + fabsf(sD));
+        const float dR = s * (sgnf(cD) * sD - sgnf(sD) * cD);  // d R / d yaw_i
+        for (int m = 0; m < 8; ++m) {
+            const float4 cm = ldc(P.cells, 8 * j + m);
+            if (cm.z == 0.f) break;  // a piece's cells come first
+            const float bx = xj + cj * cm.x - sj * cm.y, by = yj + sj * cm.x + cj * cm.y;
+            const float dx = ax - bx, dy = ay - by;
+            // projections of d on the normals (cos_i, sin_i), (-sin_i, cos_i), then piece j's
+            const float p0 = dx * ci + dy * si, p1 = dy * ci - dx * si;
+            const float p2 = dx * cj + dy * sj, p3 = dy * cj - dx * sj;
+            int best = 0;  // the first largest |projection| (the oracle's first smallest overlap)
+            float mx = fabsf(p0);
+            if (fabsf(p1) > mx) { mx = fabsf(p1); best = 1; }
+            if (fabsf(p2) > mx) { mx = fabsf(p2); best = 2; }
+            if (fabsf(p3) > mx) { mx = fabsf(p3); best = 3; }
+            const float pen = R - mx;
+            if (pen <= 0.f) continue;
+            if (j > i) {
+                cost += w * phi(phase, pen);
+                viol = fmaxf(viol, pen);
+            }
+            if (GRAD) {
+                // pen = R - sg (d.n): n, sg and d.(dn / d yaw_i) for the chosen normal
+                float nx, ny, pc, dn;
+                if (best == 0) { nx = ci; ny = si; pc = p0; dn = p1; }
+                else if (best == 1) { nx = -si; ny = ci; pc = p1; dn = -p0; }
+                else if (best == 2) { nx = cj; ny = sj; pc = p2; dn = 0.f; }
+                else { nx = -sj; ny = cj; pc = p3; dn = 0.f; }
+                const float sc = w * dphi(phase, pen), sg = sgnf(pc);
+                g[0] -= sc * sg * nx;
+                g[1] -= sc * sg * ny;
+                g[3] += sc * (dR - sg * (dax * nx + day * ny + dn));
+            }
+        }
+    }
+}
+
+// Stage-1 placement cost of one lane: the packing cost for packing problems, the tower /
+// fixed-goal cost otherwise (the mode is uniform, so the branch does not diverge).
+template <bool GRAD>
+__device__ __forceinline__ void stage1_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost,
+                                            float &viol, float (&g)[4])
+{
+    if (P.mode == SPASM_MODE_PACK)
+        pack_lane<GRAD>(P, phase, i, k, st, cost, viol, g);
+    else
+        place_lane<GRAD>(P, phase, i, k, st, cost, viol, g);
+}
+
 // ------------------------------------------------------------------------------------
 // Stage 1: sampling, placement cost/gradient and the gradient-descent loop.
 // ------------------------------------------------------------------------------------
@@ -537,6 +639,13 @@ __global__ void k_sample(KProb P, int N, uint64_t seed, int round, float *x, con
     o[0] = P.samp_x0 + P.samp_xs * u[0];
     o[1] = P.samp_y0 + P.samp_ys * u[1];
     o[2] = -3.14159265358979f + 6.28318530717959f * u[2];
+    if (P.yaw_steps > 0) {
+        // yaw on yaw_steps directions; the step index is integer arithmetic on the 24-bit
+        // draw, so no rounding can move a sample to a neighbouring direction
+        const int k24 = (int)(u[2] * 16777216.0f);
+        const int j = (int)(((long long)P.yaw_steps * k24) >> 24);
+        o[2] = -3.14159265358979f + (6.28318530717959f / (float)P.yaw_steps) * (float)j;
+    }
 }
 
 // One workgroup holds lcm(8B, 64) lanes = several particles; lane = (particle, block,
@@ -578,7 +687,7 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
         float lr;
         schedule(kk, P.k_lin1, P.eta1, P.alpha1, phase, lr);
         float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
-        place_lane<true>(P, phase, i, k, st, c, v, g);
+        stage1_lane<true>(P, phase, i, k, st, c, v, g);
 #pragma unroll
         for (int m = 1; m < 8; m <<= 1) {
             g[0] += __shfl_xor(g[0], m, 64);
@@ -602,9 +711,9 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
     }
     float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
     if (gx_out)
-        place_lane<true>(P, eval_phase, i, k, st, c, v, g);
+        stage1_lane<true>(P, eval_phase, i, k, st, c, v, g);
     else
-        place_lane<false>(P, eval_phase, i, k, st, c, v, g);
+        stage1_lane<false>(P, eval_phase, i, k, st, c, v, g);
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) {
         c += __shfl_xor(c, m, 64);

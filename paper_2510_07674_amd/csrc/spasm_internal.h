@@ -24,7 +24,10 @@ struct KProb {
     const float4 *box;       // [O][2] (cx, cy, cz, 0), (hx, hy, hz, 0)
     const float4 *blk_init;  // [B][2] (x, y, z, yaw), (cos yaw, sin yaw, 0, 0)
     const float4 *goal;      // [B][2] same layout (fixed goals)
+    const float4 *cells;     // [B][8] packing cells (ox, oy, 1, 0); (0, 0, 0, 0) past a piece's last cell
     int B, S, O, mode;
+    int yaw_steps;           // stage-1 yaw samples on yaw_steps directions (0: uniform)
+    float wall[4];           // packing walls: region x_lo, x_hi, y_lo, y_hi
     int chunk;               // spheres tested per box fetch (4, 6, 7 or 8); links padded to it
     int link_start[8];       // spheres of link k are [link_start[k-1], link_start[k])
     float a[NJ], d[NJ], ca[NJ], sa[NJ], lo[NJ], hi[NJ], q_home[NJ];

@@ -28,7 +28,8 @@ class ChainDesc(ctypes.Structure):
 
 class SkeletonDesc(ctypes.Structure):
     _fields_ = [("n_blocks", c_i32), ("mode", c_i32), ("block_edge", c_d), ("block_margin", c_d),
-                ("block_init", c_vp), ("goal", c_vp), ("grasp", c_d * 12), ("region", c_d * 4)]
+                ("block_init", c_vp), ("goal", c_vp), ("grasp", c_d * 12), ("region", c_d * 4),
+                ("pack_cells", c_vp), ("pack_off", c_vp), ("sample_yaw_steps", c_i32)]
 
 
 class ParamsDesc(ctypes.Structure):
@@ -171,6 +172,12 @@ class Problem:
         sk.goal = self._goal.ctypes.data_as(c_vp)
         sk.grasp[:] = [float(v) for v in np.asarray(prob.grasp, dtype=np.float64).ravel()]
         sk.region[:] = [float(v) for v in prob.table]
+        if getattr(prob, "pack_cells", None) is not None:
+            self._cells = np.ascontiguousarray(prob.pack_cells, dtype=np.int32)
+            self._off = np.ascontiguousarray(prob.pack_off, dtype=np.float64)
+            sk.pack_cells = self._cells.ctypes.data_as(c_vp)
+            sk.pack_off = self._off.ctypes.data_as(c_vp)
+        sk.sample_yaw_steps = int(getattr(prob, "sample_yaw_steps", 0))
         self._skel = sk
         link = np.ascontiguousarray(prob.sph_link, dtype=np.int32)
         cen = np.ascontiguousarray(prob.sph_c, dtype=np.float64)
