@@ -1,10 +1,12 @@
 """Placement-only (stage 1) sweep over sampling batch N and optimisation batch M, the
 paper's hyperparameter ablation (Sec. IV, N in 2^[9,19], M in 2^[8,13]) rerun on the
-synthetic towers-in-clutter: for each (N, M) and each trial, placement rounds
-(spasm_place_round) repeat until one satisfies; the time to that first feasible placement
-is wall clock on the host, including the per-round check of the satisfying count.
+synthetic towers-in-clutter and on the synthetic packing (Tetris) workloads: for each
+(N, M) and each trial, placement rounds (spasm_place_round) repeat until one satisfies;
+the time to that first feasible placement is wall clock on the host, including the
+per-round check of the satisfying count.
 
     python -m paper_2510_07674_amd.stage1_sweep --workload tower4 --trials 20
+    python -m paper_2510_07674_amd.stage1_sweep --workload tetris5 --nlist 9 11 13 15 --mlist 8 10 12
 """
 from __future__ import annotations
 
@@ -25,17 +27,21 @@ def main():
     ap.add_argument("--max-rounds", type=int, default=64)
     ap.add_argument("--nlog", type=int, nargs=2, default=[9, 19])
     ap.add_argument("--mlog", type=int, nargs=2, default=[8, 13])
+    ap.add_argument("--nlist", type=int, nargs="*", help="log2 N values (overrides --nlog)")
+    ap.add_argument("--mlist", type=int, nargs="*", help="log2 M values (overrides --mlog)")
     args = ap.parse_args()
+    nlogs = args.nlist or list(range(args.nlog[0], args.nlog[1] + 1))
+    mlogs = args.mlist or list(range(args.mlog[0], args.mlog[1] + 1))
     torch.cuda.set_device(0)
-    seeds = synth.certified_seeds(args.workload)[: args.trials]
+    seeds = synth.instance_seeds(args.workload)[: args.trials]
     problems = []
     for s in seeds:
         prob, pr, _ = synth.config(args.workload, s)
         problems.append(spasm.Problem(prob, pr))
     nsat_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
     rows = []
-    for nl in range(args.nlog[0], args.nlog[1] + 1):
-        for ml in range(args.mlog[0], args.mlog[1] + 1):
+    for nl in nlogs:
+        for ml in mlogs:
             N, M = 1 << nl, 1 << ml
             if M > N:
                 continue
@@ -57,7 +63,9 @@ def main():
                         break
                 times.append(time.perf_counter() - t0)
                 rounds.append(r)
-            row = {"N": N, "M": M, "mean_ms": 1e3 * float(np.mean(times)), "p50_ms": 1e3 * float(np.median(times)),
+            row = {"N": N, "M": M, "mean_ms": 1e3 * float(np.mean(times)),
+                   "ci95_ms": 1e3 * 1.96 * float(np.std(times, ddof=1)) / np.sqrt(len(times)) if len(times) > 1 else 0.0,
+                   "p50_ms": 1e3 * float(np.median(times)),
                    "mean_rounds": float(np.mean(rounds)), "solved": solved, "trials": len(problems)}
             rows.append(row)
             print(json.dumps(row), flush=True)
