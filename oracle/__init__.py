@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 LIN, QUAD = 0, 1
-MODE_TOWER, MODE_FIXED, MODE_PACK = 0, 1, 2
+MODE_TOWER, MODE_FIXED, MODE_PACK, MODE_P2P = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -43,7 +43,7 @@ class _Prob(ctypes.Structure):
                 ("block_init", ctypes.c_void_p), ("goal", ctypes.c_void_p), ("grasp", ctypes.c_void_p),
                 ("table", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("pack_cells", ctypes.c_void_p), ("pack_off", ctypes.c_void_p),
-                ("sample_yaw_steps", ctypes.c_int)]
+                ("sample_yaw_steps", ctypes.c_int), ("p2p_goal", ctypes.c_void_p)]
 
 
 _lib = None
@@ -109,6 +109,7 @@ class Oracle:
             "pack_cells": (np.ascontiguousarray(prob.pack_cells, dtype=np.int32)
                            if getattr(prob, "pack_cells", None) is not None else None),
             "pack_off": (_f64(prob.pack_off) if getattr(prob, "pack_off", None) is not None else None),
+            "p2p_goal": (_f64(prob.p2p_goal) if getattr(prob, "p2p_goal", None) is not None else None),
         }
         k = self._keep
         self.c = _Prob(prob.S, prob.O, prob.B, prob.mode, _ptr(k["dh"]).value, _ptr(k["lo"]).value,
@@ -119,7 +120,8 @@ class Oracle:
                        _ptr(k["w"]).value,
                        _ptr(k["pack_cells"]).value if k["pack_cells"] is not None else None,
                        _ptr(k["pack_off"]).value if k["pack_off"] is not None else None,
-                       int(getattr(prob, "sample_yaw_steps", 0)))
+                       int(getattr(prob, "sample_yaw_steps", 0)),
+                       _ptr(k["p2p_goal"]).value if k["p2p_goal"] is not None else None)
         self.ref = ctypes.byref(self.c)
 
     # -- geometry -------------------------------------------------------------------------
@@ -230,10 +232,16 @@ class Oracle:
         blocks at them)."""
         qg, qp, pose = _f64(qg), _f64(qp), _f64(pose)
         P, B = qg.shape[:2]
-        q = np.zeros((P, 2 * B, W, 7))
+        # a point-to-point problem has one motion (start to goal); qg, qp and pose unused
+        q = np.zeros((P, 1 if self.prob.mode == MODE_P2P else 2 * B, W, 7))
         lib().or_traj_init(self.ref, P, W, _ptr(qg), _ptr(qp), _ptr(pose), seed, self.params.mid_noise,
                            self.params.mid_candidates, _ptr(q))
         return q
+
+    def p2p_init(self, P, W, seed):
+        """Seeds of a point-to-point problem: [P, 1, W, 7] from q_home to p2p_goal."""
+        z = np.zeros((P, self.prob.B, 7))
+        return self.traj_init(z, z, W, seed, np.zeros((P, self.prob.B, 4)))
 
     # -- drivers ---------------------------------------------------------------------------
     def stage1(self, N, M, seed, rnd=0):

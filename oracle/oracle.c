@@ -235,6 +235,10 @@ static double pair_kink(double r, double sdf, double feat)
     return m;
 }
 
+/* Motion segments of a particle: transit and transfer per block, or the one motion of a
+ * point-to-point problem (mode 3). */
+static int n_seg(const or_problem *pb) { return pb->mode == 3 ? 1 : 2 * pb->B; }
+
 static double zstar(const or_problem *pb, int i)
 {
     if (pb->mode == 2) return 0.5 * pb->h; /* packing: every piece rests on the table */
@@ -595,7 +599,8 @@ static void sphere_vs_targets(const or_problem *pb, int phase, double wgt, const
             jac_point(F, L, c, gc, gq);
         }
     }
-    for (int bb = 0; bb < B; ++bb) {
+    /* a point-to-point problem has no blocks to collide with */
+    for (int bb = 0; bb < (pb->mode == 3 ? 0 : B); ++bb) {
         const double *bp;
         int movable = 0;
         if (bb < b) {
@@ -736,7 +741,7 @@ void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q
                   double *cost, double *viol, double *gq, double *gpose, double *slot_kink,
                   double *pose_kink)
 {
-    const int B = pb->B, NS = 2 * B;
+    const int B = pb->B, NS = n_seg(pb);
     const size_t qstride = (size_t)NS * W * NJ;
     const double w_smooth = pb->w[8];
 #pragma omp parallel for schedule(dynamic, 1)
@@ -774,8 +779,10 @@ void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q
                 }
             }
         }
-        double pc, pv, pkk, gpl[4 * B];
-        place_one(pb, 4, phase, pp, &pc, &pv, gpl, &pkk);
+        double pc = 0.0, pv = 0.0, pkk = INFINITY, gpl[4 * B];
+        for (int i = 0; i < 4 * B; ++i) gpl[i] = 0.0;
+        if (pb->mode != 3) /* placement variables exist only with blocks to place */
+            place_one(pb, 4, phase, pp, &pc, &pv, gpl, &pkk);
         c += pc;
         v = dmax(v, pv);
         pk = dmin(pk, pkk);
@@ -836,11 +843,12 @@ void or_traj_adam_step(const or_problem *pb, int P, int W, double *q, double *po
                        double *vq, double *mp, double *vp, const double *gq, const double *gpose,
                        double lr, int t, double b1, double b2, double eps)
 {
-    const int B = pb->B, NS = 2 * B;
+    const int B = pb->B, NS = n_seg(pb);
     const size_t qstride = (size_t)NS * W * NJ;
     for (int p = 0; p < P; ++p) {
         for (int s = 0; s < NS; ++s) {
             for (int w = 0; w < W; ++w) {
+                if (pb->mode == 3 && (w == 0 || w == W - 1)) continue; /* pinned start and goal */
                 for (int j = 0; j < NJ; ++j) {
                     size_t i = p * qstride + ((size_t)s * W + w) * NJ + j;
                     double g = gq[i];
@@ -1057,7 +1065,7 @@ double or_arm_clutter(const or_problem *pb, const double *q, const double *pose,
             const double d = r - box_sdf_ex(c, pb->boxes + 6 * o, g, NULL);
             if (d > 0.0) pen += d;
         }
-        for (int bb = 0; bb < pb->B; ++bb) {
+        for (int bb = 0; bb < (pb->mode == 3 ? 0 : pb->B); ++bb) { /* no blocks in mode 3 */
             const double *bp;
             if (bb < b || (bb == b && kind == 1))
                 bp = pose + 4 * bb;
@@ -1142,14 +1150,19 @@ void or_ik_lift(const or_problem *pb, int P, const double *pose, uint64_t seed, 
 void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, const double *q_place,
                   const double *pose, uint64_t seed, double noise, int candidates, double *q)
 {
-    const int B = pb->B, NS = 2 * B, m = (W - 1) / 2;
-    double qh[NJ];
+    const int B = pb->B, NS = n_seg(pb), m = (W - 1) / 2;
+    double qh[NJ], qgoal[NJ];
     for (int j = 0; j < NJ; ++j) qh[j] = clampd(pb->q_home[j], pb->lo[j], pb->hi[j]);
+    if (pb->mode == 3)
+        for (int j = 0; j < NJ; ++j) qgoal[j] = clampd(pb->p2p_goal[j], pb->lo[j], pb->hi[j]);
     for (int p = 0; p < P; ++p)
         for (int s = 0; s < NS; ++s) {
             int b = s / 2;
             const double *qa, *qb;
-            if (s % 2 == 0) {
+            if (pb->mode == 3) { /* the one motion: start to goal */
+                qa = qh;
+                qb = qgoal;
+            } else if (s % 2 == 0) {
                 qa = b == 0 ? qh : q_place + ((size_t)p * B + b - 1) * NJ;
                 qb = q_grasp + ((size_t)p * B + b) * NJ;
             } else {
@@ -1169,7 +1182,7 @@ void or_traj_init(const or_problem *pb, int P, int W, const double *q_grasp, con
                     h1[j] = 0.5 * (qa[j] + qc[j]);
                     h2[j] = 0.5 * (qc[j] + qb[j]);
                 }
-                const double *pp = pose + (size_t)p * B * 4;
+                const double *pp = pose ? pose + (size_t)p * B * 4 : NULL;
                 const int kind = 2 + s % 2;  /* transit or transfer interior */
                 const double sc = candidates > 1 ? or_arm_clutter(pb, qc, pp, b, kind) +
                                                        or_arm_clutter(pb, h1, pp, b, kind) +
@@ -1232,7 +1245,7 @@ void or_stage2(const or_problem *pb, int P, int W, int K, int k_lin, double eta,
                double b2, double eps, double *q, double *pose)
 {
     const int B = pb->B;
-    const size_t nq = (size_t)P * 2 * B * W * NJ, np = (size_t)P * B * 4;
+    const size_t nq = (size_t)P * n_seg(pb) * W * NJ, np = (size_t)P * B * 4;
     double *mq = calloc(nq, sizeof(double)), *vq = calloc(nq, sizeof(double));
     double *mp = calloc(np, sizeof(double)), *vp = calloc(np, sizeof(double));
     double *gq = malloc(nq * sizeof(double)), *gp = malloc(np * sizeof(double));

@@ -13,7 +13,9 @@
 #include <stdint.h>
 
 typedef struct {
-    int S, O, B, mode;              /* mode 0: tower, 1: fixed goals, 2: packing */
+    int S, O, B, mode;              /* mode 0: tower, 1: fixed goals, 2: packing,
+                                       3: point to point (one motion q_home -> p2p_goal,
+                                          trajectory [P][1][W][7], endpoints pinned) */
     const double *dh;               /* [7][3] a, d, alpha */
     const double *lo, *hi;          /* [7] */
     double tool_d;
@@ -31,6 +33,7 @@ typedef struct {
     const int32_t *pack_cells;      /* [B] cells per piece (mode 2: packing), else NULL */
     const double *pack_off;         /* [B][8][2] cell centres in the piece frame */
     int sample_yaw_steps;           /* stage-1 yaw samples: 0 uniform, n > 0 on n directions */
+    const double *p2p_goal;         /* [7] goal configuration (mode 3: point to point) */
 } or_problem;
 
 enum { OR_LIN = 0, OR_QUAD = 1 };

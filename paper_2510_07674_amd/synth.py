@@ -40,6 +40,7 @@ REGION = (0.2, 0.55, -0.35, 0.35)        # placement region (the problem's bound
 MODE_TOWER = 0                           # block b goes to tower slot b (heights (b+1/2) h)
 MODE_FIXED = 1                           # block b goes to a given fixed pose
 MODE_PACK = 2                            # polyomino pieces packed into the region (stage 1 only)
+MODE_P2P = 3                             # one motion from q_home to p2p_goal (trajectory only)
 MAX_CELLS = 8                            # cells per packing piece
 
 # weight order shared by every consumer of Params.weights()
@@ -70,6 +71,7 @@ class Problem:
     pack_off: np.ndarray = None     # (B, MAX_CELLS, 2) float64, unused rows zero
     pack_solution: np.ndarray = None  # (B, 3) one exact packing (x, y, yaw), for tests
     sample_yaw_steps: int = 0       # stage-1 yaw samples: 0 uniform, n > 0 on n directions
+    p2p_goal: np.ndarray = None     # (7,) goal configuration (MODE_P2P; the start is q_home)
 
     @property
     def S(self) -> int:
@@ -335,6 +337,22 @@ def make_packing(seed: int, B: int, rows: int, cols: int, cell: float = 0.04) ->
                                sample_yaw_steps=4)
 
 
+def make_p2p(seed: int, O: int = 20, S: int = 42) -> Problem:
+    """Draw one seeded point-to-point problem (the paper's motion-planning use, Sec. IV,
+    with synthetic scenes in place of MotionBenchMaker): a random chain and spheres as for
+    the towers, O boxes on the table as clutter, a start (q_home) and a goal configuration
+    uniform within the joint limits.  The single block of the description is a
+    placeholder that the trajectory cost does not use.  Instances whose start or goal is
+    in collision are dropped by the certificate in tests/golden (p2p_seeds)."""
+    base = make_problem(seed, B=1, O=O, S=S, mode=MODE_FIXED)
+    rng = np.random.default_rng([seed, O, S, 0x9292])
+    lo, hi = base.lo, base.hi
+    q0 = rng.uniform(lo, hi)
+    q1 = rng.uniform(lo, hi)
+    return dataclasses.replace(base, q_home=q0, mode=MODE_P2P, p2p_goal=q1,
+                               goal=np.array([[math.nan, math.nan, base.h / 2, math.nan]]))
+
+
 _SEEDS_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
                            "reachable_seeds.txt")
 
@@ -360,6 +378,12 @@ def instance_seeds(name: str) -> list:
     return certified_seeds(name)
 
 
+def p2p_seeds() -> list:
+    """Point-to-point scene seeds whose start and goal are collision-free (list written by
+    tests/golden/make_p2p_seeds.py)."""
+    return certified_seeds("p2p")
+
+
 # The five workloads.  C1..C3 are solve configurations, C4 is the differentiable-cost
 # batch, C5 is the serving mix (sizes drawn per request).
 def config(name: str, seed: int = 0):
@@ -373,6 +397,9 @@ def config(name: str, seed: int = 0):
     if name == "tower10":        # 10-block tower, 80 boxes, 20 x 32 waypoints, 48 spheres
         prob = make_problem(seed, B=10, O=80, S=48)
         return prob, Params(), SolveConfig(N1=16384, M=2048, W=32, K=300, seed=seed)
+    if name == "p2p":            # one motion between two configurations among 20 boxes
+        prob = make_p2p(seed, O=20)
+        return prob, Params(), SolveConfig(N1=0, M=256, W=32, K=100, seed=seed)
     if name == "tetris5":        # 5 pieces of 4 cells packed into a 4 x 5 box (stage 1 only)
         prob = make_packing(seed, B=5, rows=4, cols=5)
         return prob, dataclasses.replace(PACK_PARAMS), SolveConfig(N1=4096, M=1024, W=32, K=0, seed=seed)

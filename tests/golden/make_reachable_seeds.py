@@ -9,7 +9,10 @@ kinematically feasible, certified with the FP64 oracle (test infrastructure):
 Random chains (uniform DH parameters) sometimes cannot reach a top-down grasp at table
 height at all; such scenes have no solution and are not workload instances.
 
-    python tests/golden/make_reachable_seeds.py [--count 64]
+Point-to-point scenes (workload p2p) are certified when neither the start nor the goal
+configuration penetrates a box (zero clutter score: no robot sphere inside an obstacle).
+
+    python tests/golden/make_reachable_seeds.py [--count 64] [--only p2p]
 """
 import argparse
 import os
@@ -23,7 +26,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from paper_2510_07674_amd import synth  # noqa: E402
 
-WORKLOADS = ("tiny", "tower4", "tower10")
+WORKLOADS = ("tiny", "tower4", "tower10", "p2p")
 
 
 def reachable(o, prob, kind, target, rng, starts):
@@ -37,6 +40,9 @@ def reachable(o, prob, kind, target, rng, starts):
 def certify(name, seed):
     prob, pr, _ = synth.config(name, seed)
     o = oracle.Oracle(prob, pr)
+    if prob.mode == synth.MODE_P2P:
+        pose = np.zeros((prob.B, 4))
+        return o.arm_clutter(prob.q_home, pose, 0, 2) == 0.0 and o.arm_clutter(prob.p2p_goal, pose, 0, 2) == 0.0
     rng = np.random.default_rng([seed, 7])
     for b in range(prob.B):
         if not reachable(o, prob, 0, prob.block_init[b], rng, 32):
@@ -62,10 +68,20 @@ def certify(name, seed):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=64, help="certified seeds to list per workload")
+    ap.add_argument("--only", help="recompute this workload's line and keep the others")
     args = ap.parse_args()
     oracle.build(force=False)
+    path = os.path.join(HERE, "reachable_seeds.txt")
+    kept = {}
+    if args.only and os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                kept[line.split()[0]] = line.strip()
     lines = []
     for name in WORKLOADS:
+        if args.only and name != args.only and name in kept:
+            lines.append(kept[name])
+            continue
         seeds, s = [], 0
         while len(seeds) < args.count:
             if certify(name, s):
@@ -73,8 +89,8 @@ def main():
             s += 1
         lines.append(f"{name} " + " ".join(map(str, seeds)))
         print(f"{name}: {len(seeds)} of the first {s} seeds certified", flush=True)
-    with open(os.path.join(HERE, "reachable_seeds.txt"), "w") as f:
-        f.write("# scene seeds certified feasible by make_reachable_seeds.py (oracle IK)\n")
+    with open(path, "w") as f:
+        f.write("# scene seeds certified feasible by make_reachable_seeds.py (oracle IK; p2p: collision-free ends)\n")
         f.write("\n".join(lines) + "\n")
 
 

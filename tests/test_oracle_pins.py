@@ -1001,3 +1001,92 @@ def test_pack_grad_fd(orc, name):
                         assert fd == pytest.approx(g[n, i, k], abs=2e-6, rel=1e-6), (phase, n, i, k)
                         checked += 1
     assert checked > 0
+
+
+# ------------------------------------------------------------- point to point (one motion)
+def _p2p_free(seed=14):
+    """A certified point-to-point scene without its boxes (free space)."""
+    prob, pr, cfg = synth.config("p2p", seed)
+    return synth.dataclasses.replace(prob, boxes=np.zeros((0, 6))), pr, cfg
+
+
+def test_p2p_straight_line_closed_form(orc):
+    """In free space the straight, evenly spaced line from start to goal costs exactly
+    w_smooth |goal - start|^2 / (W - 1), violates nothing, and its interior waypoints
+    have zero gradient (each is the mean of its neighbours)."""
+    prob, pr, _ = _p2p_free()
+    o = orc.Oracle(prob, pr)
+    for W in (4, 16, 32):
+        t = np.linspace(0.0, 1.0, W)[:, None]
+        q = (prob.q_home[None] + t * (prob.p2p_goal - prob.q_home)[None])[None, None]
+        pose = np.zeros((1, prob.B, 4))
+        for phase in (orc.LIN, orc.QUAD):
+            c, v, gq, gp, _, _ = o.traj_cost(q, pose, phase)
+            exp = pr.w_smooth * float(np.sum((prob.p2p_goal - prob.q_home) ** 2)) / (W - 1)
+            assert c[0] == pytest.approx(exp, rel=1e-12, abs=1e-15)
+            assert v[0] == 0.0
+            assert np.abs(gq[0, 0, 1:W - 1]).max() < 1e-12
+            assert np.abs(gp).max() == 0.0
+
+
+def test_p2p_grad_fd(orc):
+    """Finite differences of the one-motion cost among the scene's boxes."""
+    rng = np.random.default_rng(41)
+    prob, pr, _ = synth.config("p2p", synth.p2p_seeds()[0])
+    o = orc.Oracle(prob, pr)
+    P, W = 3, 8
+    span = prob.hi - prob.lo
+    q = rng.uniform(prob.lo - 0.05 * span, prob.hi + 0.05 * span, size=(P, 1, W, 7))
+    pose = np.zeros((P, prob.B, 4))
+    for phase in (orc.LIN, orc.QUAD):
+        c, v, gq, gp, sk, pk = o.traj_cost(q, pose, phase)
+        assert c.min() > 0
+        checked = _fd_traj(o, q, pose, phase, gq, gp, sk, pk)
+        assert checked > 50
+
+
+def test_p2p_adam_pins_endpoints(orc):
+    """Adam moves every interior waypoint and never the start or the goal."""
+    rng = np.random.default_rng(42)
+    prob, pr, _ = synth.config("p2p", synth.p2p_seeds()[1])
+    o = orc.Oracle(prob, pr)
+    q = o.p2p_init(4, 16, seed=3)
+    pose = np.zeros((4, prob.B, 4))
+    q2, _ = o.stage2(q, pose, 20)
+    assert np.array_equal(q2[:, 0, 0], q[:, 0, 0]) and np.array_equal(q2[:, 0, -1], q[:, 0, -1])
+    assert np.all(np.abs(q2[:, 0, 1:-1] - q[:, 0, 1:-1]).max(axis=(1, 2)) > 0)
+
+
+def _philox24(seed, ctr):
+    """Four 24-bit uniforms of Philox4x64-10 at counter ctr, key (seed, 0), from numpy
+    (which advances its 256-bit counter before each block: start one below, with borrow)."""
+    v = sum(int(c) << (64 * i) for i, c in enumerate(ctr)) - 1
+    prev = np.array([(v >> (64 * i)) & (2**64 - 1) for i in range(4)], np.uint64)
+    raw = np.random.Philox(key=np.array([seed, 0], np.uint64), counter=prev).random_raw(4)
+    return (raw >> np.uint64(40)).astype(np.float64) / 2.0**24
+
+
+def test_p2p_init_rule(orc):
+    """Seeds of the one motion: exactly the start and the goal at the ends, two straight
+    pieces through the intermediate waypoint, which is the best of the candidate draws
+    (midpoint + noise from the Philox counter (particle, 0/1, candidate, 3)) by the
+    clutter score of the boxes at the draw and the two halfway points (first on ties)."""
+    prob, pr, _ = synth.config("p2p", synth.p2p_seeds()[2])
+    o = orc.Oracle(prob, pr)
+    P, W = 5, 16
+    q = o.p2p_init(P, W, seed=9)
+    m = (W - 1) // 2
+    pose = np.zeros((prob.B, 4))
+    qa, qb = np.clip(prob.q_home, prob.lo, prob.hi), np.clip(prob.p2p_goal, prob.lo, prob.hi)
+    for p in range(P):
+        assert np.array_equal(q[p, 0, 0], qa) and np.array_equal(q[p, 0, W - 1], qb)
+        best, qm = None, None
+        for c in range(pr.mid_candidates):
+            u = np.concatenate([_philox24(9, (p, k, c, 3)) for k in (0, 1)])
+            qc = np.clip(0.5 * (qa + qb) + pr.mid_noise * (2 * u[:7] - 1), prob.lo, prob.hi)
+            sc = sum(_np_clutter(o, prob, x, pose, 0, 2) for x in (qc, 0.5 * (qa + qc), 0.5 * (qc + qb)))
+            if best is None or sc < best:
+                best, qm = sc, qc
+        assert np.allclose(q[p, 0, m], qm, atol=1e-12)
+        d1, d2 = np.diff(q[p, 0, :m + 1], axis=0), np.diff(q[p, 0, m:], axis=0)
+        assert np.allclose(d1, d1[0], atol=1e-12) and np.allclose(d2, d2[0], atol=1e-12)

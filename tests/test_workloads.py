@@ -21,7 +21,7 @@ def _certificate():
 
 def test_certified_seeds_reproduce(orc):
     cert = _certificate()
-    for name in ("tiny", "tower4", "tower10"):
+    for name in ("tiny", "tower4", "tower10", "p2p"):
         seeds = synth.certified_seeds(name)
         assert len(seeds) >= 32 and seeds == sorted(set(seeds))
         for s in seeds[:2]:
