@@ -52,6 +52,7 @@ extern "C" {
 #define SPASM_MODE_TOWER 0     /* block b goes to tower slot b, centre height (b + 1/2) h */
 #define SPASM_MODE_FIXED 1     /* block b goes to goal[b] */
 #define SPASM_MODE_PACK 2      /* polyomino pieces packed into the region (stage 1 only) */
+#define SPASM_MODE_P2P 3       /* one motion from q_home to p2p_goal (trajectory only) */
 
 typedef struct spasm_problem_s *spasm_problem;
 
@@ -71,7 +72,16 @@ typedef struct {
  * in the piece frame; the pieces are packed into the region, whose four sides are the
  * walls.  Packing problems support the stage-1 entry points only (sample, placement
  * cost, stage-1 optimize, selection, order, place_round); the stage-2 entry points
- * return SPASM_EUNSUPPORTED for them. */
+ * return SPASM_EUNSUPPORTED for them.
+ * Point to point (SPASM_MODE_P2P, the motion-planning use of Sec. IV): one motion from
+ * chain->q_home to p2p_goal among the obstacles, both within the joint limits; n_blocks
+ * must be 1 (a placeholder, block_init may be NULL).  The trajectory has one segment,
+ * q [P][1][W][7], whose first and last waypoints are pinned; its cost is the stage-2
+ * cost of that segment without blocks (w_arm C_arm + w_lim C_lim + w_smooth C_smooth).
+ * The stage-2 entry points take d_pose / d_gpose = NULL (no pose variables);
+ * spasm_traj_init ignores d_qgrasp, d_qplace and d_pose; spasm_solve and
+ * spasm_solve_ttfs take N1 = 0 and skip the lift; the IK entry points and the server
+ * return SPASM_EUNSUPPORTED. */
 typedef struct {
     int32_t n_blocks;         /* B >= 1 */
     int32_t mode;             /* SPASM_MODE_TOWER, SPASM_MODE_FIXED or SPASM_MODE_PACK */
@@ -86,6 +96,7 @@ typedef struct {
                                 * pack_cells[b] ignored); cells of one piece must not overlap */
     int32_t sample_yaw_steps;  /* stage-1 yaw samples: 0 = uniform in [-pi, pi); n in 1..64 =
                                 * the n directions -pi + 2 pi j / n */
+    const double *p2p_goal;    /* host [7] goal configuration (SPASM_MODE_P2P), else NULL */
 } spasm_skeleton_desc;
 
 /* Weights and schedules.  Stage 1 (Alg. 1): k_lin1 linear steps with

@@ -80,8 +80,18 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     if (n_obs > 0 && !boxes) return fail(SPASM_EINVAL, "obstacle array is NULL");
     const int B = skel->n_blocks;
     if (B < 1 || B > MAX_B) return fail(SPASM_EUNSUPPORTED, "n_blocks=%d outside 1..%d", B, MAX_B);
-    if (skel->mode != SPASM_MODE_TOWER && skel->mode != SPASM_MODE_FIXED && skel->mode != SPASM_MODE_PACK)
+    if (skel->mode != SPASM_MODE_TOWER && skel->mode != SPASM_MODE_FIXED && skel->mode != SPASM_MODE_PACK &&
+        skel->mode != SPASM_MODE_P2P)
         return fail(SPASM_EINVAL, "unknown skeleton mode %d", skel->mode);
+    if (skel->mode == SPASM_MODE_P2P) {
+        if (B != 1) return fail(SPASM_EINVAL, "point-to-point problems take n_blocks = 1 (a placeholder)");
+        if (!skel->p2p_goal) return fail(SPASM_EINVAL, "point-to-point problems need p2p_goal");
+        if (!finite_all(skel->p2p_goal, 7)) return fail(SPASM_EINVAL, "non-finite p2p_goal");
+        for (int j = 0; j < NJ; ++j)
+            if (!(chain->q_home[j] >= chain->lo[j] && chain->q_home[j] <= chain->hi[j] &&
+                  skel->p2p_goal[j] >= chain->lo[j] && skel->p2p_goal[j] <= chain->hi[j]))
+                return fail(SPASM_EINVAL, "joint %d: start or goal outside the limits", j);
+    }
     if (skel->sample_yaw_steps < 0 || skel->sample_yaw_steps > 64)
         return fail(SPASM_EINVAL, "sample_yaw_steps=%d outside 0..64", skel->sample_yaw_steps);
     if (skel->mode == SPASM_MODE_PACK) {
@@ -91,7 +101,9 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
                 return fail(SPASM_EINVAL, "piece %d: %d cells outside 1..8", b, skel->pack_cells[b]);
         if (!finite_all(skel->pack_off, (size_t)B * 16)) return fail(SPASM_EINVAL, "non-finite cell offset");
     }
-    if (!skel->block_init) return fail(SPASM_EINVAL, "block_init is NULL");
+    if (!skel->block_init && skel->mode != SPASM_MODE_P2P) return fail(SPASM_EINVAL, "block_init is NULL");
+    const double zero_init[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *block_init = skel->block_init ? skel->block_init : zero_init;  // p2p placeholder
     if (skel->mode == SPASM_MODE_FIXED && !skel->goal) return fail(SPASM_EINVAL, "fixed goals need goal poses");
     if (!finite_all(&chain->dh[0][0], 21) || !finite_all(chain->lo, 7) || !finite_all(chain->hi, 7) ||
         !finite_all(chain->q_home, 7) || !std::isfinite(chain->tool_d))
@@ -109,7 +121,7 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     for (int o = 0; o < n_obs; ++o)
         for (int c = 3; c < 6; ++c)
             if (boxes[6 * o + c] < 0.0) return fail(SPASM_EINVAL, "obstacle %d: negative half extent", o);
-    if (!finite_all(skel->block_init, (size_t)B * 4) ||
+    if (!finite_all(block_init, (size_t)B * 4) ||
         (skel->mode == SPASM_MODE_FIXED && !finite_all(skel->goal, (size_t)B * 4)) ||
         !finite_all(&skel->grasp[0][0], 12) || !finite_all(skel->region, 4) || !std::isfinite(skel->block_edge) ||
         !std::isfinite(skel->block_margin))
@@ -192,7 +204,7 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         }
     };
     std::vector<float> init, goal, cells((size_t)B * 8 * 4, 0.f);
-    pack_poses(skel->block_init, init);
+    pack_poses(block_init, init);
     if (skel->mode == SPASM_MODE_PACK)  // [B][8] (ox, oy, 1 for a cell of the piece, 0)
         for (int b = 0; b < B; ++b)
             for (int k = 0; k < skel->pack_cells[b]; ++k) {
@@ -241,6 +253,8 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.goal = (const float4 *)(base + off_goal);
     K.cells = (const float4 *)(base + off_cells);
     K.yaw_steps = skel->sample_yaw_steps;
+    if (skel->mode == SPASM_MODE_P2P)
+        for (int j = 0; j < NJ; ++j) K.p2p_goal[j] = (float)skel->p2p_goal[j];
     for (int c = 0; c < 4; ++c) K.wall[c] = (float)skel->region[c];
     K.B = B;
     K.S = link_start[7];
@@ -345,7 +359,7 @@ extern "C" int spasm_cost_grad(spasm_problem prob, int32_t stage, int32_t phase,
     if (stage != SPASM_STAGE_TRAJ) return fail(SPASM_EINVAL, "unknown stage %d", stage);
     int rc = check_traj_shape(prob, P, W);
     if (rc) return rc;
-    if (!d_pose) return fail(SPASM_EINVAL, "d_pose is NULL");
+    if (!d_pose && prob->kp.mode != SPASM_MODE_P2P) return fail(SPASM_EINVAL, "d_pose is NULL");
     TrajArgs a{};
     a.P = P;
     a.W = W;
@@ -367,7 +381,8 @@ extern "C" int spasm_cost_adjoint(spasm_problem prob, int32_t phase, int32_t P, 
     if (phase != SPASM_PHASE_LIN && phase != SPASM_PHASE_QUAD) return fail(SPASM_EINVAL, "unknown phase %d", phase);
     int rc = check_traj_shape(prob, P, W);
     if (rc) return rc;
-    if (!d_q || !d_pose || !d_gout || !d_gq || !d_gpose) return fail(SPASM_EINVAL, "NULL buffer");
+    const bool p2p = prob->kp.mode == SPASM_MODE_P2P;  // no pose variables
+    if (!d_q || !d_gout || !d_gq || (!p2p && (!d_pose || !d_gpose))) return fail(SPASM_EINVAL, "NULL buffer");
     TrajArgs a{};
     a.P = P;
     a.W = W;
@@ -398,7 +413,7 @@ extern "C" int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int3
     if (stage != SPASM_STAGE_TRAJ) return fail(SPASM_EINVAL, "unknown stage %d", stage);
     int rc = check_traj_shape(prob, P, W);
     if (rc) return rc;
-    if (!d_pose) return fail(SPASM_EINVAL, "d_pose is NULL");
+    if (!d_pose && prob->kp.mode != SPASM_MODE_P2P) return fail(SPASM_EINVAL, "d_pose is NULL");
     if (K_total < k_end - 1) return fail(SPASM_EINVAL, "K_total=%d shorter than the step range", K_total);
     rc = ensure_attrs();
     if (rc) return rc;
@@ -540,6 +555,7 @@ extern "C" int spasm_ik_iterate(spasm_problem prob, int32_t kind, int32_t n, con
 {
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
     if (prob->kp.mode == SPASM_MODE_PACK) return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only");
+    if (prob->kp.mode == SPASM_MODE_P2P) return fail(SPASM_EUNSUPPORTED, "point-to-point problems have no blocks to grasp");
     if (kind != 0 && kind != 1) return fail(SPASM_EINVAL, "kind must be 0 (grasp) or 1 (place)");
     if (n < 1 || iters < 0 || !d_target || !d_q) return fail(SPASM_EINVAL, "bad size or NULL buffer");
     SPASM_HIP(launch_ik_iterate(prob->kp, kind, n, d_target, d_q, iters, (hipStream_t)stream));
@@ -551,6 +567,7 @@ extern "C" int spasm_ik_lift(spasm_problem prob, int32_t P, const float *d_pose,
 {
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
     if (prob->kp.mode == SPASM_MODE_PACK) return fail(SPASM_EUNSUPPORTED, "packing problems support stage 1 only");
+    if (prob->kp.mode == SPASM_MODE_P2P) return fail(SPASM_EUNSUPPORTED, "point-to-point problems have no blocks to grasp");
     if (P < 1 || iters < 0 || !d_pose || !d_qgrasp || !d_qplace) return fail(SPASM_EINVAL, "bad size or NULL buffer");
     SPASM_HIP(launch_ik_lift(prob->kp, P, d_pose, seed, iters, d_qgrasp, d_qplace, (hipStream_t)stream));
     return SPASM_OK;
@@ -562,7 +579,8 @@ extern "C" int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const f
     if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
     int rc = check_traj_shape(prob, P, W);
     if (rc) return rc;
-    if (!d_qgrasp || !d_qplace || !d_pose || !d_q) return fail(SPASM_EINVAL, "NULL buffer");
+    if (!d_q || (prob->kp.mode != SPASM_MODE_P2P && (!d_qgrasp || !d_qplace || !d_pose)))
+        return fail(SPASM_EINVAL, "NULL buffer");
     SPASM_HIP(launch_traj_init(prob->kp, P, W, d_qgrasp, d_qplace, d_pose, seed, d_q, (hipStream_t)stream));
     return SPASM_OK;
 }
@@ -633,7 +651,7 @@ int check_cfg(spasm_problem prob, const spasm_solve_config *cfg)
         if (cfg->N1 < cfg->M || cfg->N1 > MAX_SORT)
             return fail(SPASM_EUNSUPPORTED, "towers need M <= N1 <= %d (N1=%d)", MAX_SORT, cfg->N1);
     } else if (cfg->N1 != 0) {
-        return fail(SPASM_EINVAL, "fixed-goal problems take N1 = 0");
+        return fail(SPASM_EINVAL, "fixed-goal and point-to-point problems take N1 = 0");
     }
     if (cfg->K < 0) return fail(SPASM_EINVAL, "K must be >= 0");
     return check_traj_shape(prob->kp.B, cfg->M, cfg->W);
@@ -666,7 +684,8 @@ int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, c
         SPASM_HIP(launch_fixed_poses(K, M, F(L.pose), I(L.info), st));
     }
     if (after_stage1) SPASM_HIP(hipEventRecord(after_stage1, st));
-    SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg.seed, prob->ik_iters, F(L.qg), F(L.qp), st));
+    if (K.mode != SPASM_MODE_P2P)  // a point-to-point motion has its ends already
+        SPASM_HIP(launch_ik_lift(K, M, F(L.pose), cfg.seed, prob->ik_iters, F(L.qg), F(L.qp), st));
     SPASM_HIP(launch_traj_init(K, M, W, F(L.qg), F(L.qp), F(L.pose), cfg.seed, F(L.q), st));
     return SPASM_OK;
 }

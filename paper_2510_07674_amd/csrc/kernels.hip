@@ -42,6 +42,10 @@ __device__ __forceinline__ float zstar(const KProb &P, int b)
     return P.mode == 0 ? ((float)b + 0.5f) * P.h : ldc(P.goal, 2 * b).z;
 }
 
+// Motion segments per particle: transit and transfer per block, or the single motion of
+// a point-to-point problem.
+__device__ __forceinline__ int n_segments(const KProb &P) { return P.mode == SPASM_MODE_P2P ? 1 : 2 * P.B; }
+
 // Cross-lane reductions without LDS: DPP within each 16-lane row (quad_perm xor 1 and
 // xor 2, row_mirror, row_half_mirror) and the gfx950 row swaps across rows (xor 32, then
 // xor 16).  Every step combines a lane with its partner in the same operand order on
@@ -800,8 +804,9 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
         }
         const LaneBox lb = lane_box<CH>(cx, cy, cz, r, sl.active);
         collide_boxes<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, cost, viol, wf, wt);
-        collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, sl.b, own_vis, s_pose,
-                                 s_pacc, cost, viol, wf, wt);
+        if (P.mode != SPASM_MODE_P2P)  // a point-to-point problem has no blocks
+            collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, sl.b, own_vis, s_pose,
+                                     s_pacc, cost, viol, wf, wt);
     }
     wr[0] = wt[0]; wr[1] = wt[1]; wr[2] = wt[2];
     wr[3] = wf[0]; wr[4] = wf[1]; wr[5] = wf[2];
@@ -987,7 +992,7 @@ __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const S
     if (tid < 8 * MAX_B) {
         const int i = tid >> 3, k = tid & 7;
         float gp[4] = {0.f, 0.f, 0.f, 0.f};
-        if (i < P.B) place_lane<GRAD>(P, phase, i, k, s_pose, cost, viol, gp);
+        if (i < P.B && P.mode != SPASM_MODE_P2P) place_lane<GRAD>(P, phase, i, k, s_pose, cost, viol, gp);
         if (GRAD) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) gp[c] = group8_reduce(gp[c], OpSum());
@@ -1040,9 +1045,10 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     __shared__ float s_popt[2][MAX_B * 4];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const int B = P.B, W = a.W, NS = 2 * B, BW = B * W;
+    // lanes [0, BW) are the transit segments (the single motion of a p2p problem, B = 1)
+    const int B = P.B, W = a.W, NS = n_segments(P), BW = B * W;
     Slot sl;
-    sl.active = tid < 2 * BW;
+    sl.active = tid < NS * W;
     if (tid < BW) {
         sl.s = 2 * (tid / W);
         sl.w = tid % W;
@@ -1061,8 +1067,12 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
 #pragma unroll
     for (int j = 0; j < NJ; ++j) q[j] = sl.active ? a.q_in[qoff + j] : 0.f;
     if (tid < B) {
-        const float *pi = a.pose_in + ((size_t)p * B + tid) * 4;
-        set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3], P.half);
+        if (a.pose_in) {
+            const float *pi = a.pose_in + ((size_t)p * B + tid) * 4;
+            set_pose_entry(s_pose, tid, pi[0], pi[1], pi[2], pi[3], P.half);
+        } else {  // p2p problems take no poses
+            set_pose_entry(s_pose, tid, 0.f, 0.f, 0.f, 0.f, P.half);
+        }
     } else if (tid < 2 * B) {  // blockDim >= 64 >= 2 * MAX_B
         const int b = tid - B;
         const float4 a0 = ldc(P.blk_init, 2 * b), a1 = ldc(P.blk_init, 2 * b + 1);
@@ -1077,6 +1087,9 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     }
     float *s_pacc_w = s_pacc + wave * MAX_B * 4;
     if (lane < 4 * B) s_pacc_w[lane] = 0.f;
+    // each block's tie lane rewrites its entry on every evaluation; a problem without
+    // transfer segments (point to point) never does, so it must read zeros
+    if (tid < 4 * B) s_tiepose[tid] = 0.f;
     const size_t per_opt = (size_t)2 * BW * NJ + 4 * B;
     if (MODE == 2) {
         const float *om = a.opt ? a.opt + (size_t)p * 2 * per_opt : nullptr;
@@ -1108,7 +1121,8 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
             __syncthreads();
             const float bc1 = 1.f - powf(b1, (float)k), bc2s = sqrtf(1.f - powf(b2, (float)k));
             const float step = lr / bc1, ibc2 = 1.f / bc2s;
-            if (sl.active) {
+            // the start and goal of a point-to-point motion are pinned
+            if (sl.active && !(P.mode == SPASM_MODE_P2P && (sl.w == 0 || sl.w == W - 1))) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
                     float gj = g[j];
@@ -1149,7 +1163,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
 #pragma unroll
             for (int j = 0; j < NJ; ++j) a.q_out[qoff + j] = q[j];
         }
-        if (tid < 4 * B) {
+        if (tid < 4 * B && a.pose_out) {
             const int bb = tid >> 2, c = tid & 3;
             a.pose_out[((size_t)p * B + bb) * 4 + c] = s_pose[bb * 8 + c];
         }
@@ -1555,7 +1569,7 @@ __device__ __forceinline__ float arm_clutter(const KProb &P, const float (&q)[NJ
                 const float sdf = __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz) + fminf(fmaxf(fmaxf(ux, uy), uz), 0.f);
                 pen += fmaxf(sp.w - sdf, 0.f);
             }
-            for (int bb = 0; bb < P.B; ++bb) {
+            for (int bb = 0; bb < (P.mode == SPASM_MODE_P2P ? 0 : P.B); ++bb) {  // p2p: no blocks
                 float tx, ty, tz, yaw;
                 if (bb < b || (bb == b && kind == 1)) {
                     tx = pose[4 * bb];
@@ -1663,7 +1677,10 @@ __device__ __forceinline__ void segment_ends(const KProb &P, const float *qg, co
     const int B = P.B, b = s >> 1;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        if (s & 1) {
+        if (P.mode == SPASM_MODE_P2P) {  // the one motion: start to goal
+            qa[j] = fminf(fmaxf(P.q_home[j], P.lo[j]), P.hi[j]);
+            qb[j] = fminf(fmaxf(P.p2p_goal[j], P.lo[j]), P.hi[j]);
+        } else if (s & 1) {
             qa[j] = qg[((size_t)p * B + b) * NJ + j];
             qb[j] = qp[((size_t)p * B + b) * NJ + j];
         } else {
@@ -1681,7 +1698,7 @@ __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const 
                                                   const float *pose, uint64_t seed, float *q)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int grp = gid >> 3, c = gid & 7, NS = 2 * P.B, C = P.mid_candidates;
+    const int grp = gid >> 3, c = gid & 7, NS = n_segments(P), C = P.mid_candidates;
     if (grp >= nP * NS) return;  // whole 8-lane groups only
     const int p = grp / NS, s = grp % NS;
     float qa[NJ], qb[NJ], qc[NJ], h1[NJ], h2[NJ], u[8];
@@ -1696,7 +1713,7 @@ __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const 
     }
     float sc = INFINITY;
     if (c < C) {
-        const float *pp = pose + (size_t)p * P.B * 4;
+        const float *pp = pose ? pose + (size_t)p * P.B * 4 : nullptr;  // p2p: no blocks, unused
         const int kind = 2 + (s & 1);  // transit or transfer interior
         sc = C > 1 ? arm_clutter(P, qc, pp, s >> 1, kind) + arm_clutter(P, h1, pp, s >> 1, kind) +
                          arm_clutter(P, h2, pp, s >> 1, kind)
@@ -1718,7 +1735,7 @@ __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const 
 // Straight lines start -> intermediate (read from waypoint (W-1)/2, left as it is) -> goal.
 __global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float *qp, uint64_t seed, float *q)
 {
-    const int B = P.B, NS = 2 * B;
+    const int B = P.B, NS = n_segments(P);
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nP * NS * W) return;
     const int w = gid % W, s = (gid / W) % NS, p = gid / (W * NS);
@@ -1803,11 +1820,11 @@ __global__ __launch_bounds__(1024) void k_finalize(KProb P, int M, int W, const 
                                                    float *finfo)
 {
     __shared__ float s_len[16];
-    const int B = P.B, NS = 2 * B, tid = threadIdx.x;
+    const int B = P.B, NS = n_segments(P), tid = threadIdx.x;
     const int best = order[0];
     const float *qb = q + (size_t)best * NS * W * NJ;
     for (int e = tid; e < NS * W * NJ; e += blockDim.x) best_q[e] = qb[e];
-    if (tid < 4 * B) best_pose[tid] = pose[(size_t)best * 4 * B + tid];
+    if (tid < 4 * B && best_pose) best_pose[tid] = pose[(size_t)best * 4 * B + tid];
     float len = 0.f;
     for (int e = tid; e < NS * W; e += blockDim.x) {
         const int w = e % W;

@@ -173,6 +173,8 @@ extern "C" int spasm_server_submit(spasm_server srv, spasm_problem prob, const s
     if (!srv) return fail(SPASM_EINVAL, "server is NULL");
     int rc = check_cfg(prob, cfg);
     if (rc) return rc;
+    if (prob->kp.mode == SPASM_MODE_P2P)
+        return fail(SPASM_EUNSUPPORTED, "the server takes manipulation solves; use spasm_solve for point to point");
     if (!d_best_q || !d_best_pose) return fail(SPASM_EINVAL, "NULL output buffer");
     if (prob->device != srv->device) return fail(SPASM_EINVAL, "problem lives on device %d, server on %d", prob->device, srv->device);
     const size_t need = request_footprint(prob, *cfg);

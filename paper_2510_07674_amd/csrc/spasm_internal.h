@@ -28,6 +28,7 @@ struct KProb {
     int B, S, O, mode;
     int yaw_steps;           // stage-1 yaw samples on yaw_steps directions (0: uniform)
     float wall[4];           // packing walls: region x_lo, x_hi, y_lo, y_hi
+    float p2p_goal[NJ];      // point-to-point goal configuration (the start is q_home)
     int chunk;               // spheres tested per box fetch (4, 6, 7 or 8); links padded to it
     int link_start[8];       // spheres of link k are [link_start[k-1], link_start[k])
     float a[NJ], d[NJ], ca[NJ], sa[NJ], lo[NJ], hi[NJ], q_home[NJ];

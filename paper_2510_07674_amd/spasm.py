@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspasm.so")
 
 STAGE_PLACE, STAGE_TRAJ = 1, 2
+MODE_TOWER, MODE_FIXED, MODE_PACK, MODE_P2P = 0, 1, 2, 3
 PHASE_LIN, PHASE_QUAD = 0, 1
 
 c_d, c_i32, c_u64, c_vp = ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p
@@ -29,7 +30,7 @@ class ChainDesc(ctypes.Structure):
 class SkeletonDesc(ctypes.Structure):
     _fields_ = [("n_blocks", c_i32), ("mode", c_i32), ("block_edge", c_d), ("block_margin", c_d),
                 ("block_init", c_vp), ("goal", c_vp), ("grasp", c_d * 12), ("region", c_d * 4),
-                ("pack_cells", c_vp), ("pack_off", c_vp), ("sample_yaw_steps", c_i32)]
+                ("pack_cells", c_vp), ("pack_off", c_vp), ("sample_yaw_steps", c_i32), ("p2p_goal", c_vp)]
 
 
 class ParamsDesc(ctypes.Structure):
@@ -161,6 +162,8 @@ class Problem:
         L = load()
         self.prob, self.params = prob, params
         self.B = prob.B
+        # motion segments: transit and transfer per block, or one point-to-point motion
+        self.NS = 1 if int(prob.mode) == MODE_P2P else 2 * prob.B
         self._chain = chain_desc(prob)
         self._params = params_desc(params)
         self._init = np.ascontiguousarray(prob.block_init, dtype=np.float64)
@@ -178,6 +181,9 @@ class Problem:
             sk.pack_cells = self._cells.ctypes.data_as(c_vp)
             sk.pack_off = self._off.ctypes.data_as(c_vp)
         sk.sample_yaw_steps = int(getattr(prob, "sample_yaw_steps", 0))
+        if getattr(prob, "p2p_goal", None) is not None:
+            self._p2p_goal = np.ascontiguousarray(prob.p2p_goal, dtype=np.float64)
+            sk.p2p_goal = self._p2p_goal.ctypes.data_as(c_vp)
         self._skel = sk
         link = np.ascontiguousarray(prob.sph_link, dtype=np.int32)
         cen = np.ascontiguousarray(prob.sph_c, dtype=np.float64)
@@ -246,14 +252,14 @@ class Problem:
         gq = _empty(P, NS, W, 7) if grad else None
         gp = _empty(P, self.B, 4) if grad else None
         _check(load().spasm_cost_grad(self.handle, STAGE_TRAJ, phase, P, W,
-                                      _dev(q, (P, 2 * self.B, W, 7), name="q"), _dev(pose, (P, self.B, 4), name="pose"),
+                                      _dev(q, (P, self.NS, W, 7), name="q"), _dev(pose, (P, self.B, 4), name="pose"),
                                       _dev(cost), _dev(viol), _dev(gq), _dev(gp), _stream()))
         return cost, viol, gq, gp
 
     def traj_adjoint(self, q, pose, gout, phase=PHASE_LIN):
         P, NS, W, _ = q.shape
         gq, gp = _empty(P, NS, W, 7), _empty(P, self.B, 4)
-        _check(load().spasm_cost_adjoint(self.handle, phase, P, W, _dev(q, (P, 2 * self.B, W, 7), name="q"),
+        _check(load().spasm_cost_adjoint(self.handle, phase, P, W, _dev(q, (P, self.NS, W, 7), name="q"),
                                          _dev(pose, (P, self.B, 4), name="pose"), _dev(gout, (P,), name="gout"),
                                          _dev(gq), _dev(gp), _stream()))
         return gq, gp
@@ -266,7 +272,7 @@ class Problem:
         P, NS, W, _ = q.shape
         cost = _empty(P) if want_cost else None
         viol = _empty(P) if want_cost else None
-        _check(load().spasm_optimize(self.handle, STAGE_TRAJ, P, W, _dev(q, (P, 2 * self.B, W, 7), name="q"),
+        _check(load().spasm_optimize(self.handle, STAGE_TRAJ, P, W, _dev(q, (P, self.NS, W, 7), name="q"),
                                      _dev(pose, (P, self.B, 4), name="pose"), _dev(opt, name="opt"), k_begin, k_end,
                                      K_total, _dev(cost), _dev(viol), _stream()))
         return cost, viol
@@ -285,9 +291,10 @@ class Problem:
                                     self.params.ik_iters if iters is None else iters, _dev(qg), _dev(qp), _stream()))
         return qg, qp
 
-    def traj_init(self, qg, qp, W, seed, pose):
-        P = qg.shape[0]
-        q = _empty(P, 2 * self.B, W, 7)
+    def traj_init(self, qg, qp, W, seed, pose, P=None):
+        """Seeds [P, NS, W, 7]; a point-to-point problem takes qg = qp = pose = None and P."""
+        P = qg.shape[0] if qg is not None else P
+        q = _empty(P, self.NS, W, 7)
         _check(load().spasm_traj_init(self.handle, P, W, _dev(qg, (P, self.B, 7), name="qg"),
                                       _dev(qp, (P, self.B, 7), name="qp"), _dev(pose, (P, self.B, 4), name="pose"),
                                       seed, _dev(q), _stream()))
@@ -315,12 +322,12 @@ class Problem:
         if work is None:
             work = self.make_workspace(cfg)
         if best_q is None:
-            best_q = _empty(2 * self.B, cfg.W, 7)
+            best_q = _empty(self.NS, cfg.W, 7)
         if best_pose is None:
             best_pose = _empty(self.B, 4)
         res = ResultDesc()
         _check(load().spasm_solve(self.handle, ctypes.byref(c), _dev(work, name="work"), work.numel() * 4,
-                                  _dev(best_q, (2 * self.B, cfg.W, 7), name="best_q"),
+                                  _dev(best_q, (self.NS, cfg.W, 7), name="best_q"),
                                   _dev(best_pose, (self.B, 4), name="best_pose"), ctypes.byref(res), _stream()))
         out = {f: getattr(res, f) for f, _ in ResultDesc._fields_}
         return out, best_q, best_pose
@@ -334,13 +341,13 @@ class Problem:
                 _check(-1)
             work = torch.empty(n, dtype=torch.uint8, device="cuda")
         if best_q is None:
-            best_q = _empty(2 * self.B, cfg.W, 7)
+            best_q = _empty(self.NS, cfg.W, 7)
         if best_pose is None:
             best_pose = _empty(self.B, 4)
         res, att, its = ResultDesc(), c_i32(), c_i32()
         _check(load().spasm_solve_ttfs(self.handle, ctypes.byref(c), check_every, max_attempts,
                                        _dev(work, dtype=torch.uint8, name="work"), work.numel(),
-                                       _dev(best_q, (2 * self.B, cfg.W, 7), name="best_q"),
+                                       _dev(best_q, (self.NS, cfg.W, 7), name="best_q"),
                                        _dev(best_pose, (self.B, 4), name="best_pose"), ctypes.byref(res),
                                        ctypes.byref(att), ctypes.byref(its), _stream()))
         out = {f: getattr(res, f) for f, _ in ResultDesc._fields_}

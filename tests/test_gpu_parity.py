@@ -127,6 +127,11 @@ def test_place_cost_parity(sp, orc, name, phase):
 
 # ------------------------------------------------------------------- stage-2 cost
 def _states(kind, prob, pr, orc, rng, P, W):
+    if prob.mode == synth.MODE_P2P:  # one motion, no pose variables (zeros, unused)
+        pose = np.zeros((P, prob.B, 4))
+        if kind == "random":
+            return synth.random_states(rng, prob, P, W)[0][:, :1].copy(), pose
+        return orc.Oracle(prob, pr).p2p_init(P, W, seed=int(rng.integers(1000))), pose
     if kind == "random":
         return synth.random_states(rng, prob, P, W)
     # realistic: lifted and seeded by the oracle (FP64), as the solver would start
@@ -166,6 +171,7 @@ def _traj_parity(sp, orc, prob, pr, q, pose, label, phases=(0, 1)):
 
 
 @pytest.mark.parametrize("name,W,P,kind", [
+    ("p2p", 32, 16, "random"), ("p2p", 32, 16, "lifted"),
     ("tiny", 16, 48, "random"), ("tiny", 16, 48, "lifted"),
     ("tower4", 32, 6, "random"), ("tower4", 32, 6, "lifted"),
     ("tower10", 32, 2, "random"), ("tower10", 32, 3, "lifted"),
@@ -330,7 +336,7 @@ def test_place_optimize_teacher_forced(sp, orc):
     assert torch.equal(xa, xb)
 
 
-@pytest.mark.parametrize("name,W,P", [("tiny", 16, 32), ("tower4", 32, 4)])
+@pytest.mark.parametrize("name,W,P", [("tiny", 16, 32), ("tower4", 32, 4), ("p2p", 32, 16)])
 def test_traj_optimize_teacher_forced(sp, orc, name, W, P):
     """Each Adam step from the GPU state: the oracle recomputes the gradient in FP64 and
     applies its own step to the same state and moments."""
@@ -341,8 +347,9 @@ def test_traj_optimize_teacher_forced(sp, orc, name, W, P):
     q, pose = T(f32(q0)), T(f32(pose0))
     K = cfg.K
     opt = dev.opt_state(P, W)
-    nq = 2 * prob.B * W * 7
+    nq = 2 * prob.B * W * 7          # moment layout per particle: q (2B segments) then pose
     per = nq + 4 * prob.B
+    nu = int(np.prod(q0.shape[1:]))  # entries in use (one segment for point to point)
     worst = 0.0
     for k in range(1, K + 1):
         qk, pk, ok = N(q), N(pose), N(opt)
@@ -350,8 +357,8 @@ def test_traj_optimize_teacher_forced(sp, orc, name, W, P):
         q1, p1 = N(q), N(pose)
         phase, lr = o.schedule(k, pr.k_lin2(K), pr.eta2, pr.alpha2)
         _, _, gq, gp, sk, pkk = o.traj_cost(qk, pk, phase)
-        mq = ok[:, :nq].reshape(qk.shape)
-        vq = ok[:, per:per + nq].reshape(qk.shape)
+        mq = ok[:, :nu].reshape(qk.shape)
+        vq = ok[:, per:per + nu].reshape(qk.shape)
         mp = ok[:, nq:per].reshape(pk.shape)
         vp = ok[:, per + nq:].reshape(pk.shape)
         rq, rp, *_ = o.adam_step(qk, pk, mq, vq, mp, vp, gq, gp, lr, k)
