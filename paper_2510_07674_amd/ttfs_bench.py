@@ -1,8 +1,11 @@
 """Time to first solution of the whole method (the paper's solve-time measure) on the
-certified synthetic towers: spasm_solve_ttfs with a success check every `check_every`
-stage-2 iterations and up to `attempts` attempts with fresh samples.
+certified synthetic scenes: spasm_solve_ttfs with a success check every `check_every`
+stage-2 iterations and up to `attempts` attempts with fresh samples.  Reports the
+configuration-space length of the returned path too (the paper's second measure for
+its motion-planning comparison).
 
     python -m paper_2510_07674_amd.ttfs_bench --workload tower4 --solves 20
+    python -m paper_2510_07674_amd.ttfs_bench --workload p2p --solves 31 --check-every 10
 """
 from __future__ import annotations
 
@@ -31,14 +34,15 @@ def main():
         if i == 0:
             continue  # warm-up
         rows.append({"seed": s, "ms": res["total_ms"], "success": bool(res["success"]), "attempts": res["attempts"],
-                     "iters": res["iters"], "viol": res["viol"]})
+                     "iters": res["iters"], "viol": res["viol"], "length": res["length"]})
         print(json.dumps(rows[-1]), flush=True)
     ok = [r for r in rows if r["success"]]
     ms = np.array([r["ms"] for r in ok]) if ok else np.array([np.nan])
     print(json.dumps({"metric": "time to first solution (ms), solved instances", "workload": args.workload,
                       "check_every": args.check_every, "max_attempts": args.attempts, "solves": len(rows),
                       "solved": len(ok), "p50_ms": float(np.percentile(ms, 50)), "p90_ms": float(np.percentile(ms, 90)),
-                      "mean_ms": float(ms.mean()), "mean_iters_solved": float(np.mean([r["iters"] for r in ok])) if ok else None}),
+                      "mean_ms": float(ms.mean()), "mean_iters_solved": float(np.mean([r["iters"] for r in ok])) if ok else None,
+                      "mean_length_solved": float(np.mean([r["length"] for r in ok])) if ok else None}),
           flush=True)
 
 
