@@ -29,14 +29,26 @@ def main():
     ap.add_argument("--mlog", type=int, nargs=2, default=[8, 13])
     ap.add_argument("--nlist", type=int, nargs="*", help="log2 N values (overrides --nlog)")
     ap.add_argument("--mlist", type=int, nargs="*", help="log2 M values (overrides --mlog)")
+    ap.add_argument("--tuning-seeds", action="store_true",
+                    help="packing workloads: draw scenes from seeds 1000.. (disjoint from the instances 0..99)")
+    ap.add_argument("--param", nargs="*", default=[], metavar="NAME=VALUE",
+                    help="override stage-1 parameters of the workload, e.g. eta1=0.01 k_lin1=50")
     args = ap.parse_args()
     nlogs = args.nlist or list(range(args.nlog[0], args.nlog[1] + 1))
     mlogs = args.mlist or list(range(args.mlog[0], args.mlog[1] + 1))
     torch.cuda.set_device(0)
-    seeds = synth.instance_seeds(args.workload)[: args.trials]
+    if args.tuning_seeds:
+        if not args.workload.startswith("tetris"):
+            raise SystemExit("tuning seeds are defined for the packing workloads only")
+        seeds = list(range(1000, 1000 + args.trials))
+    else:
+        seeds = synth.instance_seeds(args.workload)[: args.trials]
     problems = []
     for s in seeds:
         prob, pr, _ = synth.config(args.workload, s)
+        for kv in args.param:
+            k, v = kv.split("=")
+            setattr(pr, k, type(getattr(pr, k))(v))
         problems.append(spasm.Problem(prob, pr))
     nsat_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
     rows = []
@@ -71,7 +83,8 @@ def main():
             print(json.dumps(row), flush=True)
     best = min(rows, key=lambda r: r["mean_ms"] if r["solved"] == r["trials"] else float("inf"))
     print(json.dumps({"metric": "time to first feasible placement (stage 1 only), mean over trials",
-                      "workload": args.workload, "trials": len(problems), "best": best}), flush=True)
+                      "workload": args.workload, "params": args.param, "trials": len(problems), "best": best}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -74,3 +74,22 @@ def test_p2p_rejects_block_entry_points(sp):
     with pytest.raises(sp.SpasmError):
         srv.submit(dev, cfg, 1)
     srv.close()
+
+
+@pytest.mark.parametrize("W,P", [(4, 33), (64, 5)])
+def test_p2p_smallest_and_largest_W(sp, orc, W, P):
+    """One-segment trajectories of 4 and 64 waypoints (one or two waves, ragged lanes):
+    cost parity and a solve that keeps its ends."""
+    from test_gpu_parity import _traj_parity
+    rng = np.random.default_rng(W)
+    prob, pr, cfg = synth.config("p2p", synth.p2p_seeds()[3])
+    o = orc.Oracle(prob, pr)
+    q = o.p2p_init(P, W, seed=2)
+    q[:, :, 1:-1] += rng.normal(0, 0.2, size=q[:, :, 1:-1].shape)
+    _traj_parity(sp, orc, prob, pr, q, np.zeros((P, prob.B, 4)), f"p2p W{W}")
+    dev = sp.Problem(prob, pr)
+    cfg = synth.dataclasses.replace(cfg, W=W, M=P)
+    res, bq, _ = dev.solve(cfg)
+    bq = N(bq)
+    assert bq.shape == (1, W, 7)
+    assert np.abs(bq[0, 0] - prob.q_home).max() <= 1e-6 and np.abs(bq[0, -1] - prob.p2p_goal).max() <= 1e-6

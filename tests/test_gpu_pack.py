@@ -12,6 +12,8 @@ import torch
 from paper_2510_07674_amd import synth
 from test_gpu_parity import ABS, KINK, REL, N, T, check_cost, check_grad, f32, report
 
+N_ = N  # N is also a particle count below
+
 pytestmark = pytest.mark.gpu
 
 PACK = ["tetris5", "tetris8"]
@@ -143,3 +145,50 @@ def test_pack_rejects_stage2(sp):
     with pytest.raises(sp.SpasmError):
         dev.solve(cfg)
     assert "stage 1 only" in L.spasm_last_error().decode()
+
+
+def _ragged_pieces(rng, base, B):
+    """B pieces of 1..8 distinct cells each (random lattice shapes, not a tiling)."""
+    cells = np.zeros(B, np.int32)
+    off = np.zeros((B, synth.MAX_CELLS, 2))
+    for b in range(B):
+        n = int(rng.integers(1, synth.MAX_CELLS + 1))
+        pick = rng.choice(16, n, replace=False)
+        xy = np.stack([pick % 4, pick // 4], axis=1) * base.h
+        off[b, :n] = xy - xy.mean(axis=0)
+        cells[b] = n
+    region = np.array([0.2, 0.55, -0.2, 0.2])
+    return synth.dataclasses.replace(base, block_init=np.zeros((B, 4)), goal=np.tile(base.goal[:1], (B, 1)),
+                                     pack_cells=cells, pack_off=off, pack_solution=None, table=region)
+
+
+@pytest.mark.parametrize("B,N", [(16, 1000), (1, 77), (3, 1021)])
+def test_pack_ragged_pieces(sp, orc, B, N):
+    """Any pieces of 1..8 cells, up to the 16-piece maximum (128 lanes per particle), on
+    particle counts that leave a workgroup partly filled."""
+    rng = np.random.default_rng(300 + B)
+    base, pr, _ = synth.config("tetris5", 0)
+    prob = _ragged_pieces(rng, base, B)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    x = f32(synth.random_placements(rng, prob, N))
+    for phase in (0, 1):
+        c32, v32, g32 = (N_(t) for t in dev.place_cost(T(x), phase))
+        c64, v64, g64, kink = o.place_cost(x, phase)
+        check_cost(f"pack ragged B{B} ph{phase}", c32, c64, v32, v64)
+        keep = np.broadcast_to((kink >= KINK)[:, None], g64.shape[:2])
+        check_grad(f"pack ragged B{B} ph{phase}", g32, g64, keep)
+
+
+@pytest.mark.parametrize("steps", [3, 64])
+def test_pack_sample_yaw_steps(sp, orc, steps):
+    """Yaw on a number of directions that is not a power of two, or the largest allowed:
+    the direction index is integer arithmetic on both sides, so it matches exactly."""
+    prob, pr, _ = synth.config("tetris5", 2)
+    prob = synth.dataclasses.replace(prob, sample_yaw_steps=steps)
+    dev = sp.Problem(prob, pr)
+    x32 = N_(dev.sample(20000, seed=8, rnd=3))
+    x64 = orc.Oracle(prob, pr).sample(20000, 8, 3)
+    j32 = np.round((x32[..., 2] + math.pi) / (2 * math.pi / steps)).astype(int)
+    j64 = np.round((x64[..., 2] + math.pi) / (2 * math.pi / steps)).astype(int)
+    assert np.array_equal(j32, j64) and j64.min() == 0 and j64.max() == steps - 1
+    assert np.abs(x32 - x64).max() <= 2e-6
