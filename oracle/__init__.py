@@ -67,6 +67,9 @@ def lib():
         L.or_square_pen.restype = d
         L.or_place_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp]
         L.or_traj_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_traj_cost_al.argtypes = [P, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_al_update.argtypes = [P, i, vp, d, vp]
+        L.or_stage2_al.argtypes = [P, i, i, i, i, d, d, d, d, d, i, d, vp, vp, vp]
         L.or_schedule.argtypes = [i, i, d, d, vp, vp]
         L.or_gd_step.argtypes = [P, i, vp, vp, d]
         L.or_traj_adam_step.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp, vp, vp, d, i, d, d, d]
@@ -162,6 +165,26 @@ class Oracle:
                            _ptr(gq) if grad else None, _ptr(gp) if grad else None, _ptr(sk), _ptr(pk))
         return cost, viol, gq, gp, sk, pk
 
+    def traj_cost_al(self, q, pose, lam, phase=LIN, grad=True):
+        """Stage-2 cost with the multiplier terms lambda . e (lam [P, B, 15]); also returns
+        the equality residuals e [P, B, 15] (grasp rp, rz; tie rp, rx, rz per block)."""
+        q, pose, lam = _f64(q), _f64(pose), _f64(lam)
+        P, NS, W, _ = q.shape
+        cost, viol, pk = np.zeros(P), np.zeros(P), np.zeros(P)
+        sk = np.zeros((P, NS, W))
+        e = np.zeros((P, self.prob.B, 15))
+        gq = np.zeros_like(q) if grad else None
+        gp = np.zeros_like(pose) if grad else None
+        lib().or_traj_cost_al(self.ref, phase, P, W, _ptr(q), _ptr(pose), _ptr(lam), _ptr(e), _ptr(cost),
+                              _ptr(viol), _ptr(gq) if grad else None, _ptr(gp) if grad else None, _ptr(sk),
+                              _ptr(pk))
+        return cost, viol, gq, gp, sk, pk, e
+
+    def al_update(self, e, lam, rho):
+        lam = _f64(lam).copy()
+        lib().or_al_update(self.ref, lam.shape[0], _ptr(_f64(e)), rho, _ptr(lam))
+        return lam
+
     # -- updates --------------------------------------------------------------------------
     @staticmethod
     def schedule(k, k_lin, eta, alpha):
@@ -252,12 +275,18 @@ class Oracle:
                         _ptr(x), _ptr(c), _ptr(v))
         return x, c, v
 
-    def stage2(self, q, pose, K):
+    def stage2(self, q, pose, K, lam=None):
+        """K Adam iterations; with params.al_every > 0 the augmented-Lagrangian multipliers
+        lam [P, B, 15] (zeros when None) are updated in place and returned too."""
         q, pose = _f64(q).copy(), _f64(pose).copy()
         pr = self.params
-        lib().or_stage2(self.ref, q.shape[0], q.shape[2], K, pr.k_lin2(K), pr.eta2, pr.alpha2,
-                        pr.beta1, pr.beta2, pr.adam_eps, _ptr(q), _ptr(pose))
-        return q, pose
+        every = int(getattr(pr, "al_every", 0))
+        if every > 0:
+            lam = np.zeros((q.shape[0], self.prob.B, 15)) if lam is None else _f64(lam).copy()
+        lib().or_stage2_al(self.ref, q.shape[0], q.shape[2], K, pr.k_lin2(K), pr.eta2, pr.alpha2,
+                           pr.beta1, pr.beta2, pr.adam_eps, every, float(getattr(pr, "al_rho", 0.0)), _ptr(q),
+                           _ptr(pose), _ptr(lam) if every > 0 else None)
+        return (q, pose, lam) if every > 0 else (q, pose)
 
     def initial_poses(self, x):
         """Stage-1 placements (x, y, yaw) -> stage-2 pose variables (x, y, z*, yaw)."""

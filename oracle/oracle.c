@@ -632,7 +632,8 @@ static void sphere_vs_targets(const or_problem *pb, int phase, double wgt, const
 }
 
 static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, const double *q,
-                      const double *pose, double *gq, double *gpose, slot_out *so)
+                      const double *pose, const double *lam, double *e_out, double *gq, double *gpose,
+                      slot_out *so)
 {
     const int b = s / 2, tau = s % 2;
     const double h = pb->h;
@@ -684,6 +685,21 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
             gp[i] = 2.0 * w_start * rp[i];
             gu[i] = 2.0 * w_start * rz[i];
         }
+        /* equality residual e = (rp, rz) of block b, components 0..5; multiplier term
+         * lambda . e of the augmented Lagrangian */
+        if (e_out)
+            for (int i = 0; i < 3; ++i) {
+                e_out[15 * b + i] = rp[i];
+                e_out[15 * b + 3 + i] = rz[i];
+            }
+        if (lam) {
+            const double *l = lam + 15 * b;
+            so->cost += dot3(l, rp) + dot3(l + 3, rz);
+            for (int i = 0; i < 3; ++i) {
+                gp[i] += l[i];
+                gu[i] += l[3 + i];
+            }
+        }
         jac_point(F, 7, TB.p, gp, gq);
         jac_dir(F, 7, u, gu, gq);
     }
@@ -709,6 +725,22 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
             gp[i] = 2.0 * w_tie * rp[i];
             gx[i] = 2.0 * w_tie * rx[i];
             gz[i] = 2.0 * w_tie * rz[i];
+        }
+        /* equality residual (rp, rx, rz) of block b, components 6..14 */
+        if (e_out)
+            for (int i = 0; i < 3; ++i) {
+                e_out[15 * b + 6 + i] = rp[i];
+                e_out[15 * b + 9 + i] = rx[i];
+                e_out[15 * b + 12 + i] = rz[i];
+            }
+        if (lam) {
+            const double *l = lam + 15 * b + 6;
+            so->cost += dot3(l, rp) + dot3(l + 3, rx) + dot3(l + 6, rz);
+            for (int i = 0; i < 3; ++i) {
+                gp[i] += l[i];
+                gx[i] += l[3 + i];
+                gz[i] += l[6 + i];
+            }
         }
         jac_point(F, 7, TB.p, gp, gq);
         jac_dir(F, 7, ux, gx, gq);
@@ -741,6 +773,16 @@ void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q
                   double *cost, double *viol, double *gq, double *gpose, double *slot_kink,
                   double *pose_kink)
 {
+    or_traj_cost_al(pb, phase, P, W, q, pose, NULL, NULL, cost, viol, gq, gpose, slot_kink, pose_kink);
+}
+
+/* The stage-2 cost with the augmented Lagrangian's multiplier terms: lam [P][B][15]
+ * (nullable) adds lambda . e for each block's equality residual e (grasp alignment rp,
+ * rz: components 0..5; tie rp, rx, rz: 6..14); e_out [P][B][15] (nullable) receives e. */
+void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double *q, const double *pose,
+                     const double *lam, double *e_out, double *cost, double *viol, double *gq, double *gpose,
+                     double *slot_kink, double *pose_kink)
+{
     const int B = pb->B, NS = n_seg(pb);
     const size_t qstride = (size_t)NS * W * NJ;
     const double w_smooth = pb->w[8];
@@ -761,7 +803,9 @@ void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q
                 double *g = gqp ? gqp + ((size_t)s * W + w) * NJ : scratch;
                 if (!gqp)
                     for (int j = 0; j < NJ; ++j) scratch[j] = 0.0;
-                traj_slot(pb, phase, W, s, w, qp + ((size_t)s * W + w) * NJ, pp, g, gpo, &so);
+                traj_slot(pb, phase, W, s, w, qp + ((size_t)s * W + w) * NJ, pp,
+                          lam ? lam + (size_t)p * B * 15 : NULL, e_out ? e_out + (size_t)p * B * 15 : NULL, g,
+                          gpo, &so);
                 c += so.cost;
                 v = dmax(v, so.viol);
                 pk = dmin(pk, so.pose_kink);
@@ -1241,8 +1285,27 @@ void or_stage1(const or_problem *pb, int N, int M, uint64_t seed, int round, int
     free(x);
 }
 
+/* Augmented-Lagrangian multiplier step: lambda <- lambda + rho * 2 w * e for the grasp
+ * (w_start, components 0..5) and tie (w_tie, 6..14) residuals of every block; the penalty
+ * w |e|^2 is the (mu / 2) |e|^2 of the method of multipliers with mu = 2 w. */
+void or_al_update(const or_problem *pb, int P, const double *e, double rho, double *lam)
+{
+    const double w_start = pb->w[3], w_tie = pb->w[4];
+    for (size_t i = 0; i < (size_t)P * pb->B * 15; ++i)
+        lam[i] += rho * 2.0 * ((i % 15) < 6 ? w_start : w_tie) * e[i];
+}
+
 void or_stage2(const or_problem *pb, int P, int W, int K, int k_lin, double eta, double alpha, double b1,
                double b2, double eps, double *q, double *pose)
+{
+    or_stage2_al(pb, P, W, K, k_lin, eta, alpha, b1, b2, eps, 0, 0.0, q, pose, NULL);
+}
+
+/* Stage 2 with the augmented-Lagrangian outer loop (Sec. III-B): after the evaluation of
+ * every al_every-th iteration the multipliers take the step above with that evaluation's
+ * residuals (al_every = 0: the plain penalty method; lam may be NULL then). */
+void or_stage2_al(const or_problem *pb, int P, int W, int K, int k_lin, double eta, double alpha, double b1,
+                  double b2, double eps, int al_every, double al_rho, double *q, double *pose, double *lam)
 {
     const int B = pb->B;
     const size_t nq = (size_t)P * n_seg(pb) * W * NJ, np = (size_t)P * B * 4;
@@ -1250,13 +1313,17 @@ void or_stage2(const or_problem *pb, int P, int W, int K, int k_lin, double eta,
     double *mp = calloc(np, sizeof(double)), *vp = calloc(np, sizeof(double));
     double *gq = malloc(nq * sizeof(double)), *gp = malloc(np * sizeof(double));
     double *c = malloc((size_t)P * sizeof(double)), *v = malloc((size_t)P * sizeof(double));
+    double *e = calloc((size_t)P * B * 15, sizeof(double));
     for (int k = 1; k <= K; ++k) {
         int phase;
         double lr;
         or_schedule(k, k_lin, eta, alpha, &phase, &lr);
-        or_traj_cost(pb, phase, P, W, q, pose, c, v, gq, gp, NULL, NULL);
+        or_traj_cost_al(pb, phase, P, W, q, pose, al_every > 0 ? lam : NULL, al_every > 0 ? e : NULL, c, v, gq,
+                        gp, NULL, NULL);
         or_traj_adam_step(pb, P, W, q, pose, mq, vq, mp, vp, gq, gp, lr, k, b1, b2, eps);
+        if (al_every > 0 && k % al_every == 0) or_al_update(pb, P, e, al_rho, lam);
     }
+    free(e);
     free(v);
     free(c);
     free(gp);

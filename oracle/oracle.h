@@ -49,6 +49,11 @@ void or_place_cost(const or_problem *pb, int dim, int phase, int N, const double
 void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q,
                   const double *pose, double *cost, double *viol, double *gq,
                   double *gpose, double *slot_kink, double *pose_kink);
+void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double *q,
+                     const double *pose, const double *lam, double *e_out, double *cost,
+                     double *viol, double *gq, double *gpose, double *slot_kink,
+                     double *pose_kink);
+void or_al_update(const or_problem *pb, int P, const double *e, double rho, double *lam);
 
 void or_schedule(int k, int k_lin, double eta, double alpha, int *phase, double *lr);
 void or_gd_step(const or_problem *pb, int N, double *x, const double *g, double lr);
@@ -75,4 +80,7 @@ void or_stage1(const or_problem *pb, int N, int M, uint64_t seed, int round, int
                double *viol_out);
 void or_stage2(const or_problem *pb, int P, int W, int K, int k_lin, double eta,
                double alpha, double b1, double b2, double eps, double *q, double *pose);
+void or_stage2_al(const or_problem *pb, int P, int W, int K, int k_lin, double eta,
+                  double alpha, double b1, double b2, double eps, int al_every, double al_rho,
+                  double *q, double *pose, double *lam);
 #endif

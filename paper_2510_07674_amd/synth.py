@@ -124,6 +124,10 @@ class Params:
     # success test and stage-1 retries
     sat_eps: float = 1e-3
     retries: int = 4
+    # augmented-Lagrangian outer loop of stage 2 (Sec. III-B): every al_every iterations
+    # the grasp and tie multipliers step by al_rho * 2w * residual; 0 = plain penalties
+    al_every: int = 0
+    al_rho: float = 1.0
 
     def weights(self) -> np.ndarray:
         return np.array([getattr(self, "w_" + n) for n in WEIGHT_NAMES], dtype=np.float64)

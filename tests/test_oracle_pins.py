@@ -1090,3 +1090,116 @@ def test_p2p_init_rule(orc):
         assert np.allclose(q[p, 0, m], qm, atol=1e-12)
         d1, d2 = np.diff(q[p, 0, :m + 1], axis=0), np.diff(q[p, 0, m:], axis=0)
         assert np.allclose(d1, d1[0], atol=1e-12) and np.allclose(d2, d2[0], atol=1e-12)
+
+
+# ------------------------------------------------- augmented Lagrangian (stage 2, opt-in)
+def _np_residuals(o, prob, q, pose):
+    """Equality residuals written out in numpy from the (pinned) forward kinematics:
+    block frame T_B = T_E G^-1; grasp (rp = t_B - t_init, rz = R_B e_z - e_z) at the
+    first transfer waypoint and tie (rp = t_B - t_P, rx = R_B e_x - (cos, sin, 0),
+    rz = R_B e_z - e_z) at the last, per block."""
+    P, NS, W, _ = q.shape
+    G = np.vstack([prob.grasp, [0, 0, 0, 1]])
+    Gi = np.linalg.inv(G)
+    e = np.zeros((P, prob.B, 15))
+    for p in range(P):
+        for b in range(prob.B):
+            for w, off in ((0, 0), (W - 1, 6)):
+                F = o.fk(q[p, 2 * b + 1, w]).reshape(9, 12)
+                R, t = F[8, :9].reshape(3, 3), F[8, 9:]
+                TE = np.eye(4)
+                TE[:3, :3], TE[:3, 3] = R, t
+                TB = TE @ Gi
+                if off == 0:
+                    e[p, b, 0:3] = TB[:3, 3] - prob.block_init[b, :3]
+                    e[p, b, 3:6] = TB[:3, 2] - [0, 0, 1]
+                else:
+                    yaw = pose[p, b, 3]
+                    e[p, b, 6:9] = TB[:3, 3] - pose[p, b, :3]
+                    e[p, b, 9:12] = TB[:3, 0] - [math.cos(yaw), math.sin(yaw), 0]
+                    e[p, b, 12:15] = TB[:3, 2] - [0, 0, 1]
+    return e
+
+
+def test_al_residuals_and_multiplier_term(orc):
+    rng = np.random.default_rng(51)
+    prob, pr, _ = synth.config("tower4", 1)
+    o = orc.Oracle(prob, pr)
+    q, pose = synth.random_states(rng, prob, 3, 8)
+    lam = rng.normal(0, 2, (3, prob.B, 15))
+    c0, v0, *_ = o.traj_cost(q, pose, orc.LIN)
+    c1, v1, gq, gp, sk, pk, e = o.traj_cost_al(q, pose, lam, orc.LIN)
+    assert np.allclose(e, _np_residuals(o, prob, q, pose), atol=1e-12)
+    assert np.allclose(c1 - c0, (lam * e).sum(axis=(1, 2)), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(v0, v1)  # the violation is the plain residual norm
+    cz, _, gqz, gpz, *_ = o.traj_cost_al(q, pose, np.zeros_like(lam), orc.LIN)
+    c0g, _, gq0, gp0, *_ = o.traj_cost(q, pose, orc.LIN)
+    assert np.array_equal(cz, c0g) and np.array_equal(gqz, gq0) and np.array_equal(gpz, gp0)
+
+
+def test_al_grad_fd(orc):
+    rng = np.random.default_rng(52)
+    for name in ("tiny", "tower4"):
+        prob, pr, _ = synth.config(name, 2)
+        o = orc.Oracle(prob, pr)
+        q, pose = synth.random_states(rng, prob, 2, 6)
+        lam = rng.normal(0, 2, (2, prob.B, 15))
+        c, v, gq, gp, sk, pk, e = o.traj_cost_al(q, pose, lam, orc.LIN)
+        hstep, checked = 1e-6, 0
+        for p in range(2):
+            for s in range(q.shape[1]):
+                for w in (0, q.shape[2] - 1):  # the grasp and tie waypoints carry the multipliers
+                    if sk[p, s, w] < 100 * hstep:
+                        continue
+                    for j in range(7):
+                        qp, qm = q[p:p + 1].copy(), q[p:p + 1].copy()
+                        qp[0, s, w, j] += hstep
+                        qm[0, s, w, j] -= hstep
+                        fd = (o.traj_cost_al(qp, pose[p:p + 1], lam[p:p + 1], orc.LIN, grad=False)[0][0]
+                              - o.traj_cost_al(qm, pose[p:p + 1], lam[p:p + 1], orc.LIN, grad=False)[0][0]) / (2 * hstep)
+                        # each waypoint copy carries its own gradient (boundary copies apart)
+                        assert fd == pytest.approx(gq[p, s, w, j], abs=3e-6, rel=1e-6), (name, p, s, w, j)
+                        checked += 1
+            if pk[p] >= 100 * hstep and prob.mode == synth.MODE_TOWER:
+                for b in range(prob.B):
+                    for k in range(4):
+                        pp_, pm_ = pose[p:p + 1].copy(), pose[p:p + 1].copy()
+                        pp_[0, b, k] += hstep
+                        pm_[0, b, k] -= hstep
+                        fd = (o.traj_cost_al(q[p:p + 1], pp_, lam[p:p + 1], orc.LIN, grad=False)[0][0]
+                              - o.traj_cost_al(q[p:p + 1], pm_, lam[p:p + 1], orc.LIN, grad=False)[0][0]) / (2 * hstep)
+                        assert fd == pytest.approx(gp[p, b, k], abs=3e-6, rel=1e-6), (name, p, b, k)
+                        checked += 1
+        assert checked > 20
+
+
+def test_al_update_rule(orc):
+    """One iteration with al_every = 1 from zero multipliers leaves lambda = rho 2w e(q0)
+    (w_start on the grasp components, w_tie on the tie components); al_every = 0 is the
+    plain method."""
+    rng = np.random.default_rng(53)
+    prob, pr, cfg = synth.config("tiny", 3)
+    o0 = orc.Oracle(prob, pr)
+    q, pose = synth.random_states(rng, prob, 2, 8)
+    pose = np.repeat(prob.goal[None], 2, axis=0)
+    *_, e0 = o0.traj_cost_al(q, pose, np.zeros((2, prob.B, 15)), orc.LIN)
+    pr_al = synth.dataclasses.replace(pr, al_every=1, al_rho=0.5)
+    o1 = orc.Oracle(prob, pr_al)
+    q1, p1, lam = o1.stage2(q, pose, 1)
+    w = np.array([pr.w_start] * 6 + [pr.w_tie] * 9)
+    assert np.allclose(lam, 0.5 * 2 * w * e0, rtol=1e-12, atol=1e-15)
+    qp, pp = o0.stage2(q, pose, 1)
+    assert np.array_equal(q1, qp)  # the first step uses lambda = 0: same as plain
+    # two iterations, step by step from the primitives under the K = 2 schedule: each
+    # evaluation uses the current multipliers, then they step with its residuals
+    K = 2
+    q2, _, lam2 = o1.stage2(q, pose, K)
+    qk, lamk = q.copy(), np.zeros((2, prob.B, 15))
+    mq, vq = np.zeros_like(q), np.zeros_like(q)
+    mp, vp = np.zeros_like(pose), np.zeros_like(pose)
+    for k in range(1, K + 1):
+        phase, lr = o0.schedule(k, pr.k_lin2(K), pr.eta2, pr.alpha2)
+        _, _, gq, gp, _, _, ek = o0.traj_cost_al(qk, pose, lamk, phase)
+        qk, _, mq, vq, mp, vp = o0.adam_step(qk, pose, mq, vq, mp, vp, gq, gp, lr, k)
+        lamk = lamk + 0.5 * 2 * w * ek
+    assert np.allclose(lam2, lamk, rtol=1e-12, atol=1e-12) and np.allclose(q2, qk, rtol=0, atol=1e-14)
