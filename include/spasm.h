@@ -114,6 +114,14 @@ typedef struct {
     double ik_lambda, ik_noise, mid_noise;
     double sat_eps;   /* a particle satisfies the constraints when its violation < sat_eps */
     int32_t retries;  /* stage-1 resampling rounds when nothing satisfies */
+    /* Augmented-Lagrangian outer loop of stage 2 (Sec. III-B), off when al_every = 0: each
+     * block's grasp residual e (position, z axis: 6 components) and tie residual (position,
+     * x axis, z axis: 9) get multipliers lambda, the cost gains lambda . e, and after the
+     * evaluation of every al_every-th iteration lambda += al_rho * 2 w e (w_start, w_tie).
+     * Multipliers start at zero in spasm_solve / spasm_solve_ttfs; the server takes
+     * al_every = 0 only. */
+    int32_t al_every;
+    double al_rho;
 } spasm_params;
 
 typedef struct {
@@ -174,6 +182,13 @@ int spasm_cost_grad(spasm_problem prob, int32_t stage, int32_t phase, int32_t P,
                     const float *d_x, const float *d_pose, float *d_cost, float *d_viol,
                     float *d_gx, float *d_gpose, void *stream);
 
+/* Stage-2 cost and gradient with the augmented-Lagrangian multiplier terms (see
+ * spasm_params.al_every): d_lambda [P][B][15] (grasp residual components 0..5, tie
+ * residual 6..14 per block), read only; otherwise as spasm_cost_grad at stage 2. */
+int spasm_cost_grad_al(spasm_problem prob, int32_t phase, int32_t P, int32_t W, const float *d_q,
+                       const float *d_pose, const float *d_lambda, float *d_cost, float *d_viol,
+                       float *d_gq, float *d_gpose, void *stream);
+
 /* Adjoint of the stage-2 cost for reverse-mode differentiation: given d_gout [P]
  * (dL/dcost per particle) writes d_gq = gout * dcost/dq [P][2B][W][7] and
  * d_gpose = gout * dcost/dpose [P][B][4]. */
@@ -189,7 +204,9 @@ int spasm_cost_adjoint(spasm_problem prob, int32_t phase, int32_t P, int32_t W, 
  * stage 2 (Sec. III-B): Adam on d_x = q [P][2B][W][7] and, for towers, d_pose [P][B][4];
  *   K_total sets k_lin2; boundary copies get the sum of their gradients;
  *   d_opt holds the Adam moments [P][(2B*W*7 + 4B) * 2] floats (m then v per particle),
- *   read at entry and written back at exit; zero it before step 1.
+ *   and, when al_every > 0, each particle's 15B multipliers after its moments (row of
+ *   (2B*W*7 + 4B) * 2 + 15B floats); read at entry and written back at exit; zero it
+ *   before step 1.
  * d_cost / d_viol (nullable, [P]) receive the quadratic-phase cost and violation of the
  * final state. */
 int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, float *d_x,

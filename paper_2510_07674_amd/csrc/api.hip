@@ -44,6 +44,23 @@ int fail(int code, const char *fmt, ...)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Optimiser state per particle: Adam m and v over (2B W 7 joint angles, 4B pose values),
+// then, with the augmented Lagrangian, the 15 multipliers of each block.
+size_t opt_floats(const KProb &K, int W)
+{
+    const size_t per = (size_t)2 * K.B * W * NJ + 4 * K.B;
+    return 2 * per + (K.al_every > 0 ? (size_t)15 * K.B : 0);
+}
+
+void set_opt_layout(const KProb &K, int W, TrajArgs &a)
+{
+    a.opt_stride = (int)opt_floats(K, W);
+    if (K.al_every > 0 && a.opt) {
+        a.lam = a.opt + (opt_floats(K, W) - (size_t)15 * K.B);
+        a.lam_stride = a.opt_stride;
+    }
+}
+
 int ensure_attrs()
 {
     int dev = 0;
@@ -147,6 +164,8 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         return fail(SPASM_EINVAL, "ik_restarts=%d outside 1..8", prm->ik_restarts);
     if (prm->mid_candidates < 1 || prm->mid_candidates > 8)
         return fail(SPASM_EINVAL, "mid_candidates=%d outside 1..8", prm->mid_candidates);
+    if (prm->al_every < 0 || !(prm->al_rho >= 0.0 && std::isfinite(prm->al_rho)))
+        return fail(SPASM_EINVAL, "al_every must be >= 0 and al_rho finite and >= 0");
     const double pv[] = {prm->eta1, prm->alpha1, prm->lin_frac2, prm->eta2, prm->alpha2, prm->beta1, prm->beta2,
                          prm->adam_eps, prm->ik_lambda, prm->ik_noise, prm->mid_noise, prm->sat_eps};
     if (!finite_all(pv, sizeof(pv) / sizeof(pv[0]))) return fail(SPASM_EINVAL, "non-finite parameter");
@@ -253,6 +272,8 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.goal = (const float4 *)(base + off_goal);
     K.cells = (const float4 *)(base + off_cells);
     K.yaw_steps = skel->sample_yaw_steps;
+    K.al_every = prm->al_every;
+    K.al_rho = (float)prm->al_rho;
     if (skel->mode == SPASM_MODE_P2P)
         for (int j = 0; j < NJ; ++j) K.p2p_goal[j] = (float)skel->p2p_goal[j];
     for (int c = 0; c < 4; ++c) K.wall[c] = (float)skel->region[c];
@@ -396,6 +417,31 @@ extern "C" int spasm_cost_adjoint(spasm_problem prob, int32_t phase, int32_t P, 
     return SPASM_OK;
 }
 
+extern "C" int spasm_cost_grad_al(spasm_problem prob, int32_t phase, int32_t P, int32_t W, const float *d_q,
+                                  const float *d_pose, const float *d_lambda, float *d_cost, float *d_viol, float *d_gq,
+                                  float *d_gpose, void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (phase != SPASM_PHASE_LIN && phase != SPASM_PHASE_QUAD) return fail(SPASM_EINVAL, "unknown phase %d", phase);
+    int rc = check_traj_shape(prob, P, W);
+    if (rc) return rc;
+    if (!d_q || !d_lambda || (!d_pose && prob->kp.mode != SPASM_MODE_P2P)) return fail(SPASM_EINVAL, "NULL buffer");
+    TrajArgs a{};
+    a.P = P;
+    a.W = W;
+    a.phase = phase;
+    a.q_in = d_q;
+    a.pose_in = d_pose;
+    a.cost = d_cost;
+    a.viol = d_viol;
+    a.gq = d_gq;
+    a.gpose = d_gpose;
+    a.lam = const_cast<float *>(d_lambda);  // read only: no multiplier step outside optimise
+    a.lam_stride = 15 * prob->kp.B;
+    SPASM_HIP(launch_traj(prob->kp, (d_gq || d_gpose) ? 1 : 0, a, (hipStream_t)stream));
+    return SPASM_OK;
+}
+
 extern "C" int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, float *d_x, float *d_pose,
                               float *d_opt, int32_t k_begin, int32_t k_end, int32_t K_total, float *d_cost,
                               float *d_viol, void *stream)
@@ -417,6 +463,8 @@ extern "C" int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int3
     if (K_total < k_end - 1) return fail(SPASM_EINVAL, "K_total=%d shorter than the step range", K_total);
     rc = ensure_attrs();
     if (rc) return rc;
+    if (prob->kp.al_every > 0 && !d_opt)
+        return fail(SPASM_EINVAL, "the augmented Lagrangian keeps its multipliers in d_opt: it must not be NULL");
     TrajArgs a{};
     a.P = P;
     a.W = W;
@@ -425,6 +473,7 @@ extern "C" int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int3
     a.q_out = d_x;
     a.pose_out = d_pose;
     a.opt = d_opt;
+    set_opt_layout(prob->kp, W, a);
     a.k_begin = k_begin;
     a.k_end = k_end;
     a.k_lin2 = (int)std::lround(prob->lin_frac2 * K_total);
@@ -628,6 +677,7 @@ SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c)
         L.done = take(4);
     }
     L.pose = take(M * B * 4 * 4);
+    if (K.al_every > 0) L.lam = take(M * B * 15 * 4);
     L.qg = take(M * B * NJ * 4);
     L.qp = take(M * B * NJ * 4);
     L.q = take(M * 2 * B * W * NJ * 4);
@@ -712,8 +762,7 @@ extern "C" size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_co
 namespace spasm {
 size_t stage2_opt_bytes(const KProb &K, const spasm_solve_config &cfg)
 {
-    const size_t B = K.B;
-    return (size_t)cfg.M * 2 * (2 * B * cfg.W * NJ + 4 * B) * sizeof(float);
+    return (size_t)cfg.M * opt_floats(K, cfg.W) * sizeof(float);
 }
 }  // namespace spasm
 
@@ -780,6 +829,7 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
         a.q_out = F(L.q);
         a.pose_out = F(L.pose);
         a.opt = F(opt_off);
+        set_opt_layout(K, ca.W, a);
         a.k_lin2 = (int)std::lround(prob->lin_frac2 * ca.K);
         a.cost = F(L.c2);
         a.viol = F(L.v2);
@@ -859,6 +909,11 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     a.k_lin2 = (int)std::lround(prob->lin_frac2 * cfg->K);
     a.cost = F(L.c2);
     a.viol = F(L.v2);
+    if (K.al_every > 0) {  // multipliers start at zero
+        SPASM_HIP(launch_zero(I(L.lam), (size_t)cfg->M * K.B * 15 * sizeof(float), st));
+        a.lam = F(L.lam);
+        a.lam_stride = 15 * K.B;
+    }
     SPASM_HIP(hipEventRecord(ev[3], st));
     SPASM_HIP(launch_traj(K, 2, a, st));
     SPASM_HIP(hipEventRecord(ev[4], st));

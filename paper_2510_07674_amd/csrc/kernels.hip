@@ -825,6 +825,16 @@ __device__ __forceinline__ void links_reverse(const KProb &P, const float (&q)[N
     }
 }
 
+// Augmented-Lagrangian multipliers of one particle: lam [B][15] (nullable: plain
+// penalties) for each block's grasp residual (components 0..5) and tie residual (6..14);
+// with update set, the lanes that evaluate a residual also take the multiplier step
+// lam += rho 2w e with it (the next evaluation sees the new values).
+struct AlState {
+    float *lam;
+    bool update;
+    float rho;
+};
+
 // Cost (and gradient) of one slot: arm spheres vs obstacles and blocks, held block,
 // grasp alignment, tie to the placement, joint limits.  Smoothness and the placement
 // cost are added by the caller.  GRAD: g[7] receives dC/dq of this slot, the pose
@@ -833,7 +843,7 @@ __device__ __forceinline__ void links_reverse(const KProb &P, const float (&q)[N
 template <bool GRAD, int CH>
 __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
                                           const float *s_pose, float *s_pacc, float *s_tiepose, float &cost,
-                                          float &viol, float (&g)[NJ])
+                                          float &viol, float (&g)[NJ], const AlState &al)
 {
     const bool own_vis = sl.tau == 0 && sl.w < W - 1;
     float wr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -892,9 +902,20 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
         const float c2 = rp0 * rp0 + rp1 * rp1 + rp2 * rp2 + rz0 * rz0 + rz1 * rz1 + rz2 * rz2;
         cost += w_st * c2;
         viol = fmaxf(viol, sqrtf(c2));
+        float l[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (al.lam) {
+            float *lb = al.lam + 15 * sl.b;
+            const float e[6] = {rp0, rp1, rp2, rz0, rz1, rz2};
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                l[c] = lb[c];
+                cost += l[c] * e[c];
+                if (al.update) lb[c] = l[c] + al.rho * 2.f * w_st * e[c];
+            }
+        }
         if (GRAD) {
-            const float f0 = 2.f * w_st * rp0, f1 = 2.f * w_st * rp1, f2 = 2.f * w_st * rp2;
-            const float h0 = 2.f * w_st * rz0, h1 = 2.f * w_st * rz1, h2 = 2.f * w_st * rz2;
+            const float f0 = 2.f * w_st * rp0 + l[0], f1 = 2.f * w_st * rp1 + l[1], f2 = 2.f * w_st * rp2 + l[2];
+            const float h0 = 2.f * w_st * rz0 + l[3], h1 = 2.f * w_st * rz1 + l[4], h2 = 2.f * w_st * rz2 + l[5];
             ef[0] += f0;
             ef[1] += f1;
             ef[2] += f2;
@@ -917,10 +938,21 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
                          rz1 * rz1 + rz2 * rz2;
         cost += w_t * c2;
         viol = fmaxf(viol, sqrtf(c2));
+        float l[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (al.lam) {
+            float *lb = al.lam + 15 * sl.b + 6;
+            const float e[9] = {rp0, rp1, rp2, rx0, rx1, rx2, rz0, rz1, rz2};
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                l[c] = lb[c];
+                cost += l[c] * e[c];
+                if (al.update) lb[c] = l[c] + al.rho * 2.f * w_t * e[c];
+            }
+        }
         if (GRAD) {
-            const float f0 = 2.f * w_t * rp0, f1 = 2.f * w_t * rp1, f2 = 2.f * w_t * rp2;
-            const float hx0 = 2.f * w_t * rx0, hx1 = 2.f * w_t * rx1, hx2 = 2.f * w_t * rx2;
-            const float hz0 = 2.f * w_t * rz0, hz1 = 2.f * w_t * rz1, hz2 = 2.f * w_t * rz2;
+            const float f0 = 2.f * w_t * rp0 + l[0], f1 = 2.f * w_t * rp1 + l[1], f2 = 2.f * w_t * rp2 + l[2];
+            const float hx0 = 2.f * w_t * rx0 + l[3], hx1 = 2.f * w_t * rx1 + l[4], hx2 = 2.f * w_t * rx2 + l[5];
+            const float hz0 = 2.f * w_t * rz0 + l[6], hz1 = 2.f * w_t * rz1 + l[7], hz2 = 2.f * w_t * rz2 + l[8];
             ef[0] += f0;
             ef[1] += f1;
             ef[2] += f2;
@@ -973,9 +1005,9 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
 template <bool GRAD, int CH>
 __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
                                               const float *s_pose, float *s_pacc_wave, float *s_tiepose,
-                                              float *s_placeg, float &cost, float &viol, float (&g)[NJ])
+                                              float *s_placeg, float &cost, float &viol, float (&g)[NJ], const AlState &al)
 {
-    slot_eval<GRAD, CH>(P, phase, sl, W, q, s_pose, s_pacc_wave, s_tiepose, cost, viol, g);
+    slot_eval<GRAD, CH>(P, phase, sl, W, q, s_pose, s_pacc_wave, s_tiepose, cost, viol, g, al);
     const float w_s = P.w[W_SMOOTH];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -1091,8 +1123,10 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     // transfer segments (point to point) never does, so it must read zeros
     if (tid < 4 * B) s_tiepose[tid] = 0.f;
     const size_t per_opt = (size_t)2 * BW * NJ + 4 * B;
+    const size_t ostride = a.opt_stride ? (size_t)a.opt_stride : 2 * per_opt;  // floats per particle in opt
+    AlState al{a.lam ? a.lam + (size_t)p * a.lam_stride : nullptr, false, P.al_rho};
     if (MODE == 2) {
-        const float *om = a.opt ? a.opt + (size_t)p * 2 * per_opt : nullptr;
+        const float *om = a.opt ? a.opt + (size_t)p * ostride : nullptr;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             s_mv[(0 * NJ + j) * blockDim.x + tid] = (om && sl.active) ? om[(sl.s * W + sl.w) * NJ + j] : 0.f;
@@ -1113,7 +1147,8 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
             float lr;
             schedule(k, a.k_lin2, P.eta2, P.alpha2, phase, lr);
             float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            particle_eval<true, CH>(P, phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+            al.update = al.lam && P.al_every > 0 && k % P.al_every == 0;
+            particle_eval<true, CH>(P, phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g, al);
             if (sl.active && sl.w == W - 1)
                 for (int j = 0; j < NJ; ++j) s_tie[0][sl.s][j] = g[j];
             if (sl.active && sl.w == 0)
@@ -1168,7 +1203,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
             a.pose_out[((size_t)p * B + bb) * 4 + c] = s_pose[bb * 8 + c];
         }
         if (a.opt) {
-            float *om = a.opt + (size_t)p * 2 * per_opt;
+            float *om = a.opt + (size_t)p * ostride;
             if (sl.active)
                 for (int j = 0; j < NJ; ++j) {
                     om[(sl.s * W + sl.w) * NJ + j] = s_mv[(0 * NJ + j) * blockDim.x + tid];
@@ -1181,7 +1216,9 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
         }
         if (!a.cost && !a.viol) return;
         float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        particle_eval<false, CH>(P, 1, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+        // the final evaluation ranks particles by the plain cost (no multiplier terms)
+        particle_eval<false, CH>(P, 1, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g,
+                                 AlState{nullptr, false, 0.f});
         cost = wave_sum(cost);
         viol = wave_max(viol);
         if (lane == 0) {
@@ -1203,7 +1240,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
 
     // MODE 0 / 1: one evaluation
     float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    particle_eval<MODE == 1, CH>(P, a.phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g);
+    particle_eval<MODE == 1, CH>(P, a.phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g, al);
     cost = wave_sum(cost);
     viol = wave_max(viol);
     if (lane == 0) {

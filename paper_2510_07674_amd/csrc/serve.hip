@@ -175,6 +175,8 @@ extern "C" int spasm_server_submit(spasm_server srv, spasm_problem prob, const s
     if (rc) return rc;
     if (prob->kp.mode == SPASM_MODE_P2P)
         return fail(SPASM_EUNSUPPORTED, "the server takes manipulation solves; use spasm_solve for point to point");
+    if (prob->kp.al_every > 0)
+        return fail(SPASM_EUNSUPPORTED, "the server runs the plain penalty method (al_every = 0)");
     if (!d_best_q || !d_best_pose) return fail(SPASM_EINVAL, "NULL output buffer");
     if (prob->device != srv->device) return fail(SPASM_EINVAL, "problem lives on device %d, server on %d", prob->device, srv->device);
     const size_t need = request_footprint(prob, *cfg);

@@ -29,6 +29,8 @@ struct KProb {
     int yaw_steps;           // stage-1 yaw samples on yaw_steps directions (0: uniform)
     float wall[4];           // packing walls: region x_lo, x_hi, y_lo, y_hi
     float p2p_goal[NJ];      // point-to-point goal configuration (the start is q_home)
+    int al_every;            // augmented Lagrangian: multiplier step every al_every iterations (0: off)
+    float al_rho;            // multiplier step al_rho * 2w * residual
     int chunk;               // spheres tested per box fetch (4, 6, 7 or 8); links padded to it
     int link_start[8];       // spheres of link k are [link_start[k-1], link_start[k])
     float a[NJ], d[NJ], ca[NJ], sa[NJ], lo[NJ], hi[NJ], q_home[NJ];
@@ -69,6 +71,11 @@ struct TrajArgs {
     const float *gout;  // adjoint scale per particle (nullable)
     float *cost, *viol; // nullable
     float *gq, *gpose;  // nullable
+    // augmented-Lagrangian multipliers [particle][B][15] at lam + p * lam_stride (nullable:
+    // plain penalties); optimise updates them every P.al_every iterations
+    float *lam;
+    int lam_stride;
+    int opt_stride;     // floats per particle in opt (0: the two moment blocks only)
 };
 // mode 0: cost only, 1: cost + gradient (scaled by gout if given), 2: optimise
 hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st);
@@ -84,6 +91,9 @@ struct ServeSolve {
 // nwg = total particles of the class; d_solves sorted by `first`, device memory
 hipError_t launch_serve(int chunk, int threads, int nwg, const ServeSolve *d_solves, int nsolve, hipStream_t st);
 int traj_threads(int B, int W);
+// optimiser state floats per particle (Adam moments, then multipliers when al_every > 0)
+size_t opt_floats(const KProb &K, int W);
+void set_opt_layout(const KProb &K, int W, TrajArgs &a);
 // raise the dynamic-LDS ceilings of the sort and optimise kernels
 hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes);
 
@@ -122,7 +132,7 @@ int check_traj_shape(int B, int P, int W);
 
 // Workspace layout of one solve (offsets in bytes from the workspace base).
 struct SolveLayout {
-    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, pose, qg, qp, q, c2, v2, ord2, nsat2, info, finfo, total;
+    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, pose, lam, qg, qp, q, c2, v2, ord2, nsat2, info, finfo, total;
 };
 SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c);
 int check_cfg(spasm_problem prob, const spasm_solve_config *cfg);

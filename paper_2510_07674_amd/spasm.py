@@ -37,7 +37,7 @@ class ParamsDesc(ctypes.Structure):
     _fields_ = [("w", c_d * 9), ("k_lin1", c_i32), ("k_quad1", c_i32), ("eta1", c_d), ("alpha1", c_d),
                 ("lin_frac2", c_d), ("eta2", c_d), ("alpha2", c_d), ("beta1", c_d), ("beta2", c_d),
                 ("adam_eps", c_d), ("ik_iters", c_i32), ("ik_restarts", c_i32), ("mid_candidates", c_i32), ("ik_lambda", c_d), ("ik_noise", c_d),
-                ("mid_noise", c_d), ("sat_eps", c_d), ("retries", c_i32)]
+                ("mid_noise", c_d), ("sat_eps", c_d), ("retries", c_i32), ("al_every", c_i32), ("al_rho", c_d)]
 
 
 class SolveConfigDesc(ctypes.Structure):
@@ -63,6 +63,7 @@ SYMBOLS = {
     "spasm_sample": ([c_vp, c_i32, c_u64, c_i32, c_vp, c_vp], c_i32),
     "spasm_cost_grad": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
     "spasm_cost_adjoint": ([c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
+    "spasm_cost_grad_al": ([c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
     "spasm_optimize": ([c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp], c_i32),
     "spasm_select_topm": ([c_i32, c_vp, c_i32, c_vp, c_vp], c_i32),
     "spasm_order": ([c_i32, c_vp, c_vp, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
@@ -149,6 +150,8 @@ def params_desc(pr) -> ParamsDesc:
     p.w[:] = [float(v) for v in pr.weights()]
     for name in ("k_lin1", "k_quad1", "ik_iters", "ik_restarts", "mid_candidates", "retries"):
         setattr(p, name, int(getattr(pr, name)))
+    p.al_every = int(getattr(pr, "al_every", 0))
+    p.al_rho = float(getattr(pr, "al_rho", 1.0))
     for name in ("eta1", "alpha1", "lin_frac2", "eta2", "alpha2", "beta1", "beta2", "adam_eps", "ik_lambda",
                  "ik_noise", "mid_noise", "sat_eps"):
         setattr(p, name, float(getattr(pr, name)))
@@ -256,6 +259,17 @@ class Problem:
                                       _dev(cost), _dev(viol), _dev(gq), _dev(gp), _stream()))
         return cost, viol, gq, gp
 
+    def traj_cost_al(self, q, pose, lam, phase=PHASE_LIN, grad=True):
+        """Stage-2 cost with the multiplier terms lambda . e; lam [P, B, 15]."""
+        P, NS, W, _ = q.shape
+        cost, viol = _empty(P), _empty(P)
+        gq = _empty(P, NS, W, 7) if grad else None
+        gp = _empty(P, self.B, 4) if grad else None
+        _check(load().spasm_cost_grad_al(self.handle, phase, P, W, _dev(q, (P, self.NS, W, 7), name="q"),
+                                         _dev(pose, (P, self.B, 4), name="pose"), _dev(lam, (P, self.B, 15), name="lam"),
+                                         _dev(cost), _dev(viol), _dev(gq), _dev(gp), _stream()))
+        return cost, viol, gq, gp
+
     def traj_adjoint(self, q, pose, gout, phase=PHASE_LIN):
         P, NS, W, _ = q.shape
         gq, gp = _empty(P, NS, W, 7), _empty(P, self.B, 4)
@@ -265,7 +279,9 @@ class Problem:
         return gq, gp
 
     def opt_state(self, P, W):
-        return torch.zeros(P, 2 * (2 * self.B * W * 7 + 4 * self.B), dtype=torch.float32, device="cuda")
+        """Optimiser state rows: Adam m and v, then the 15B multipliers with al_every > 0."""
+        al = 15 * self.B if int(getattr(self.params, "al_every", 0)) > 0 else 0
+        return torch.zeros(P, 2 * (2 * self.B * W * 7 + 4 * self.B) + al, dtype=torch.float32, device="cuda")
 
     def traj_optimize(self, q, pose, opt, k_begin, k_end, K_total, want_cost=True):
         """In place on q, pose and opt (Adam moments)."""

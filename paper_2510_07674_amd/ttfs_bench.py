@@ -24,12 +24,17 @@ def main():
     ap.add_argument("--solves", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=25)
     ap.add_argument("--attempts", type=int, default=4)
+    ap.add_argument("--param", nargs="*", default=[], metavar="NAME=VALUE",
+                    help="override solver parameters, e.g. al_every=10 al_rho=0.1")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     seeds = synth.certified_seeds(args.workload)[: args.solves + 1]
     rows = []
     for i, s in enumerate(seeds):
         prob, pr, cfg = synth.config(args.workload, s)
+        for kv in args.param:
+            k, v = kv.split("=")
+            setattr(pr, k, type(getattr(pr, k))(v))
         res, _, _ = spasm.Problem(prob, pr).solve_ttfs(cfg, args.check_every, args.attempts)
         if i == 0:
             continue  # warm-up
@@ -39,6 +44,7 @@ def main():
     ok = [r for r in rows if r["success"]]
     ms = np.array([r["ms"] for r in ok]) if ok else np.array([np.nan])
     print(json.dumps({"metric": "time to first solution (ms), solved instances", "workload": args.workload,
+                      "params": args.param,
                       "check_every": args.check_every, "max_attempts": args.attempts, "solves": len(rows),
                       "solved": len(ok), "p50_ms": float(np.percentile(ms, 50)), "p90_ms": float(np.percentile(ms, 90)),
                       "mean_ms": float(ms.mean()), "mean_iters_solved": float(np.mean([r["iters"] for r in ok])) if ok else None,
