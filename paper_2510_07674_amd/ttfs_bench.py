@@ -26,15 +26,19 @@ def main():
     ap.add_argument("--attempts", type=int, default=4)
     ap.add_argument("--param", nargs="*", default=[], metavar="NAME=VALUE",
                     help="override solver parameters, e.g. al_every=10 al_rho=0.1")
+    ap.add_argument("--K", type=int, help="override the stage-2 iteration count")
+    ap.add_argument("--first", type=int, default=0, help="start at this position of the certified seed list")
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    seeds = synth.certified_seeds(args.workload)[: args.solves + 1]
+    seeds = synth.certified_seeds(args.workload)[args.first: args.first + args.solves + 1]
     rows = []
     for i, s in enumerate(seeds):
         prob, pr, cfg = synth.config(args.workload, s)
         for kv in args.param:
             k, v = kv.split("=")
             setattr(pr, k, type(getattr(pr, k))(v))
+        if args.K is not None:
+            cfg = synth.dataclasses.replace(cfg, K=args.K)
         res, _, _ = spasm.Problem(prob, pr).solve_ttfs(cfg, args.check_every, args.attempts)
         if i == 0:
             continue  # warm-up
