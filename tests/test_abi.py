@@ -151,3 +151,62 @@ def test_topm_and_place_shapes():
     assert L.spasm_select_topm_large(20000, dummy, 0, dummy, None, 0, None) == -1
     assert L.spasm_select_topm_large(20000, dummy, 8, dummy, None, 0, None) == -1   # no workspace
     assert L.spasm_place_round(None, 100, 10, 0, 0, None, 0, dummy, None, None, dummy, None) == -1
+
+
+@pytest.mark.parametrize("mutate", [
+    "pack_no_cells", "pack_zero_cells", "pack_nine_cells", "pack_nan_offset", "yaw_steps_high", "yaw_steps_neg",
+    "p2p_two_blocks", "p2p_no_goal", "p2p_goal_outside", "p2p_start_outside", "al_every_neg", "al_rho_neg",
+    "al_rho_nan",
+])
+def test_problem_create_rejects_mode_options(mutate):
+    """Host validation of the packing, point-to-point and augmented-Lagrangian options:
+    every bad description is refused with SPASM_EINVAL before any device call."""
+    from paper_2510_07674_amd import synth
+    if mutate.startswith("pack") or mutate.startswith("yaw"):
+        prob, params, _ = synth.config("tetris5", 0)
+    elif mutate.startswith("p2p"):
+        prob, params, _ = synth.config("p2p", synth.p2p_seeds()[0])
+    else:
+        prob, params, _ = synth.config("tower4", 0)
+    a = _problem_args(prob, params)
+    cells = np.ascontiguousarray(prob.pack_cells if prob.pack_cells is not None else np.ones(prob.B), np.int32)
+    off = np.ascontiguousarray(prob.pack_off if prob.pack_off is not None else np.zeros((prob.B, 8, 2)), np.float64)
+    goal = np.ascontiguousarray(prob.p2p_goal if prob.p2p_goal is not None else np.zeros(7), np.float64)
+    a["keep"] = a["keep"] + (cells, off, goal)
+    if prob.mode == synth.MODE_PACK:
+        a["sk"].pack_cells = cells.ctypes.data_as(ctypes.c_void_p)
+        a["sk"].pack_off = off.ctypes.data_as(ctypes.c_void_p)
+        a["sk"].sample_yaw_steps = 4
+    if prob.mode == synth.MODE_P2P:
+        a["sk"].p2p_goal = goal.ctypes.data_as(ctypes.c_void_p)
+    if mutate == "pack_no_cells":
+        a["sk"].pack_cells = None
+    elif mutate == "pack_zero_cells":
+        cells[1] = 0
+    elif mutate == "pack_nine_cells":
+        cells[2] = 9
+    elif mutate == "pack_nan_offset":
+        off[0, 1, 0] = math.nan
+    elif mutate == "yaw_steps_high":
+        a["sk"].sample_yaw_steps = 65
+    elif mutate == "yaw_steps_neg":
+        a["sk"].sample_yaw_steps = -1
+    elif mutate == "p2p_two_blocks":
+        a["sk"].n_blocks = 2
+        init2 = np.zeros((2, 4))
+        a["keep"] = a["keep"] + (init2,)
+        a["sk"].block_init = init2.ctypes.data_as(ctypes.c_void_p)
+    elif mutate == "p2p_no_goal":
+        a["sk"].p2p_goal = None
+    elif mutate == "p2p_goal_outside":
+        goal[3] = 3.0
+    elif mutate == "p2p_start_outside":
+        a["chain"].q_home[5] = -3.0
+    elif mutate == "al_every_neg":
+        a["pr"].al_every = -1
+    elif mutate == "al_rho_neg":
+        a["pr"].al_rho = -0.5
+    elif mutate == "al_rho_nan":
+        a["pr"].al_rho = math.nan
+    rc, msg = _create(a)
+    assert rc == -1 and msg, (rc, msg)
