@@ -518,6 +518,7 @@ extern "C" int spasm_select_topm_large(int32_t N, const float *d_key, int32_t M,
     const size_t need = topm_workspace(N, M);
     if (work_bytes < need || (need && !d_work))
         return fail(SPASM_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    if (need && ((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace is not 256-byte aligned");
     rc = ensure_attrs();
     if (rc) return rc;
     SPASM_HIP(launch_topm(N, d_key, M, d_idx, d_work, (hipStream_t)stream));

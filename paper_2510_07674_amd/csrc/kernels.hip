@@ -1413,6 +1413,168 @@ __global__ __launch_bounds__(1024) void k_topm_round(int n, const float *cost, c
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Top-M beyond one workgroup's sort (Alg. 1 ArgSort[:M] for N up to 2^20): radix select.
+// Three counting passes over the ordered 32-bit cost (digits of 11, 11 and 10 bits) find
+// the value T of the M-th smallest key, the number of keys below it, and how many keys
+// equal to T are still needed; the keys below T and the first of the keys equal to T in
+// index order are collected (exactly the M smallest (cost, index) pairs) and sorted in
+// one workgroup.  State in the workspace: prefix, mask, need, below.
+// ------------------------------------------------------------------------------------
+constexpr int RS_KEYS = 4096;  // keys per workgroup in the counting passes
+
+__device__ __forceinline__ void rs_digit(int pass, int &shift, int &bins)
+{
+    shift = pass == 0 ? 21 : pass == 1 ? 10 : 0;
+    bins = pass == 2 ? 1024 : 2048;
+}
+
+__global__ __launch_bounds__(1024) void k_rs_init(int M, uint32_t *state, uint32_t *hist, uint32_t *counter)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        state[0] = 0;  // prefix: the bits of T fixed so far
+        state[1] = 0;  // mask of those bits
+        state[2] = (uint32_t)M;  // keys still needed among those matching the prefix
+        state[3] = 0;  // keys known to lie below T
+        *counter = 0;
+    }
+    for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
+}
+
+__global__ __launch_bounds__(1024) void k_rs_hist(int n, const float *cost, int pass, const uint32_t *state,
+                                                  uint32_t *hist)
+{
+    __shared__ uint32_t s_h[2048];
+    int shift, bins;
+    rs_digit(pass, shift, bins);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < bins; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = state[0], mask = state[1];
+    const int lo = blockIdx.x * RS_KEYS, hi = min(n, lo + RS_KEYS);
+    for (int e = lo + tid; e < hi; e += blockDim.x) {
+        const uint32_t u = ordered_bits(cost[e]);
+        if ((u & mask) == prefix) atomicAdd(&s_h[(u >> shift) & (uint32_t)(bins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int i = tid; i < bins; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// One workgroup of 1024 threads, two bins each: the bin in which the running count
+// reaches need fixes the next digit of T; the histogram is cleared for the next pass.
+__global__ __launch_bounds__(1024) void k_rs_pick(int pass, uint32_t *state, uint32_t *hist)
+{
+    __shared__ uint32_t s_w[16];
+    int shift, bins;
+    rs_digit(pass, shift, bins);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t h0 = 2 * tid < bins ? hist[2 * tid] : 0u, h1 = 2 * tid + 1 < bins ? hist[2 * tid + 1] : 0u;
+    const uint32_t prefix = state[0], mask = state[1], need = state[2], below0 = state[3];
+    uint32_t incl = h0 + h1;  // inclusive scan over the threads' pairs
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += s_w[w];
+    incl += off;
+    const uint32_t excl = incl - h0 - h1;
+    int b = -1;
+    uint32_t below = 0;
+    if (excl < need && need <= excl + h0) {
+        b = 2 * tid;
+        below = excl;
+    } else if (excl + h0 < need && need <= incl) {
+        b = 2 * tid + 1;
+        below = excl + h0;
+    }
+    __syncthreads();  // every thread has read the state and its bins
+    if (b >= 0) {
+        state[0] = prefix | ((uint32_t)b << shift);
+        state[1] = mask | ((uint32_t)(bins - 1) << shift);
+        state[2] = need - below;
+        state[3] = below0 + below;
+    }
+    if (2 * tid < 2048) hist[2 * tid] = 0;
+    if (2 * tid + 1 < 2048) hist[2 * tid + 1] = 0;
+}
+
+// keys equal to T per workgroup range
+__global__ __launch_bounds__(1024) void k_rs_eqcount(int n, const float *cost, const uint32_t *state, uint32_t *wg_eq)
+{
+    __shared__ uint32_t s_w[16];
+    const uint32_t T = state[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = blockIdx.x * RS_KEYS, hi = min(n, lo + RS_KEYS);
+    uint32_t c = 0;
+    for (int e = lo + tid; e < hi; e += blockDim.x) c += ordered_bits(cost[e]) == T ? 1u : 0u;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) s_w[wave] = c;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_w[w];
+        wg_eq[blockIdx.x] = t;
+    }
+}
+
+// Collect the M keys: every key below T, and the keys equal to T while their rank in
+// index order (over the whole input) is below need.
+__global__ __launch_bounds__(1024) void k_rs_collect(int n, const float *cost, const uint32_t *state,
+                                                     const uint32_t *wg_eq, int M, uint32_t *counter,
+                                                     unsigned long long *surv)
+{
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_base;
+    const uint32_t T = state[0], need = state[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    if (tid == 0) {
+        uint32_t b = 0;
+        for (int g = 0; g < (int)blockIdx.x; ++g) b += wg_eq[g];
+        s_base = b;
+    }
+    __syncthreads();
+    uint32_t run = s_base;
+    const int lo = blockIdx.x * RS_KEYS, hi = min(n, lo + RS_KEYS);
+    for (int e0 = lo; e0 < hi; e0 += blockDim.x) {
+        const int e = e0 + tid;
+        uint32_t u = 0;
+        bool lt = false, eq = false;
+        if (e < hi) {
+            u = ordered_bits(cost[e]);
+            lt = u < T;
+            eq = u == T;
+        }
+        const unsigned long long key = ((unsigned long long)u << 32) | (uint32_t)e;
+        if (lt) {
+            const uint32_t slot = atomicAdd(counter, 1u);
+            if (slot < (uint32_t)M) surv[slot] = key;
+        }
+        const unsigned long long bm = __ballot(eq);
+        const uint32_t in_wave = (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+        if (lane == 0) s_w[wave] = (uint32_t)__popcll(bm);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < nwave; ++w) {
+            const uint32_t c = s_w[w];
+            if (w < wave) before += c;
+            total += c;
+        }
+        if (eq && run + before + in_wave < need) {
+            const uint32_t slot = atomicAdd(counter, 1u);
+            if (slot < (uint32_t)M) surv[slot] = key;
+        }
+        run += total;
+        __syncthreads();  // s_w is rewritten next round
+    }
+}
+
 // Placement round output: particles in satisfying-first order with their cost and
 // violation.
 __global__ void k_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,
@@ -1987,32 +2149,40 @@ hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *vio
     return hipGetLastError();
 }
 
+static size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the radix select: state (4 words) and counter in the first 256 bytes, the
+// 2048-bin histogram, the per-workgroup counts of keys equal to T, then M 64-bit keys.
 size_t topm_workspace(int n, int M)
 {
     if (n <= MAX_SORT) return 0;
-    return 2 * (size_t)((n + MAX_SORT - 1) / MAX_SORT) * (size_t)M * sizeof(unsigned long long);
+    const size_t G = (size_t)(n + RS_KEYS - 1) / RS_KEYS;
+    return 256 + 2048 * sizeof(uint32_t) + align_up256(G * sizeof(uint32_t)) + (size_t)M * sizeof(unsigned long long);
 }
 
 hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *ws, hipStream_t st)
 {
     if (n <= MAX_SORT) return launch_sort_keys(0, n, cost, nullptr, 0.f, M, out_idx, nullptr, nullptr, st);
-    unsigned long long *buf[2] = {(unsigned long long *)ws,
-                                  (unsigned long long *)ws + (size_t)((n + MAX_SORT - 1) / MAX_SORT) * M};
-    const unsigned long long *in = nullptr;
-    int count = n, r = 0;
-    const size_t shm_full = (size_t)MAX_SORT * sizeof(unsigned long long);
-    while (count > MAX_SORT) {  // M < MAX_SORT: every round shrinks count
-        const int G = (count + MAX_SORT - 1) / MAX_SORT;
-        hipLaunchKernelGGL(k_topm_round, dim3(G), dim3(1024), shm_full, st, count, in ? nullptr : cost, in, MAX_SORT,
-                           M, buf[r & 1], (int32_t *)nullptr);
-        count = (G - 1) * M + std::min(M, count - (G - 1) * MAX_SORT);
-        in = buf[r & 1];
-        ++r;
+    const int G = (n + RS_KEYS - 1) / RS_KEYS;
+    char *w = (char *)ws;
+    uint32_t *state = (uint32_t *)w, *counter = state + 8;
+    uint32_t *hist = (uint32_t *)(w + 256);
+    uint32_t *wg_eq = (uint32_t *)(w + 256 + 2048 * sizeof(uint32_t));
+    unsigned long long *surv =
+        (unsigned long long *)(w + 256 + 2048 * sizeof(uint32_t) + align_up256((size_t)G * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_rs_init, dim3(1), dim3(1024), 0, st, M, state, hist, counter);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(1024), 0, st, n, cost, pass, (const uint32_t *)state, hist);
+        hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(1024), 0, st, pass, state, hist);
     }
+    hipLaunchKernelGGL(k_rs_eqcount, dim3(G), dim3(1024), 0, st, n, cost, (const uint32_t *)state, wg_eq);
+    hipLaunchKernelGGL(k_rs_collect, dim3(G), dim3(1024), 0, st, n, cost, (const uint32_t *)state,
+                       (const uint32_t *)wg_eq, M, counter, surv);
     int npow = 1;
-    while (npow < count) npow <<= 1;
-    hipLaunchKernelGGL(k_topm_round, dim3(1), dim3(1024), (size_t)npow * sizeof(unsigned long long), st, count,
-                       (const float *)nullptr, in, count, M, (unsigned long long *)nullptr, out_idx);
+    while (npow < M) npow <<= 1;
+    hipLaunchKernelGGL(k_topm_round, dim3(1), dim3(1024), (size_t)npow * sizeof(unsigned long long), st, M,
+                       (const float *)nullptr, (const unsigned long long *)surv, M, M, (unsigned long long *)nullptr,
+                       out_idx);
     return hipGetLastError();
 }
 

@@ -433,7 +433,7 @@ def select_topm(key, M):
 
 
 def select_topm_large(key, M, work=None):
-    """select_topm for up to 2^20 keys (chunked rounds); allocates its workspace if not given."""
+    """select_topm for up to 2^20 keys (radix select); allocates its workspace if not given."""
     N = key.shape[0]
     need = load().spasm_select_topm_workspace(N, M)
     if work is None and need:

@@ -142,7 +142,10 @@ def test_topm_and_place_shapes():
     from paper_2510_07674_amd import spasm
     L = spasm.load()
     assert L.spasm_select_topm_workspace(16384, 2048) == 0
-    assert L.spasm_select_topm_workspace(131072, 256) == 2 * 8 * 256 * 8
+    # radix select: state (256 B), 2048-bin histogram, per-workgroup counts of 4096 keys
+    # rounded up to 256 B, M (cost bits, index) survivors
+    assert L.spasm_select_topm_workspace(131072, 256) == 256 + 2048 * 4 + 256 + 256 * 8
+    assert L.spasm_select_topm_workspace(1 << 20, 8192) == 256 + 2048 * 4 + 1024 + 8192 * 8
     assert L.spasm_select_topm_workspace(1 << 21, 256) == 0          # too many keys
     assert L.spasm_select_topm_workspace(20000, 8193) == 0           # M too large for chunking
     dummy = ctypes.c_void_p(256)
@@ -150,6 +153,9 @@ def test_topm_and_place_shapes():
     assert L.spasm_select_topm_large(20000, dummy, 8193, dummy, None, 0, None) == -4
     assert L.spasm_select_topm_large(20000, dummy, 0, dummy, None, 0, None) == -1
     assert L.spasm_select_topm_large(20000, dummy, 8, dummy, None, 0, None) == -1   # no workspace
+    need = L.spasm_select_topm_workspace(20000, 8)
+    assert L.spasm_select_topm_large(20000, dummy, 8, dummy, ctypes.c_void_p(256 + 4), need, None) == -1
+    assert "256-byte aligned" in L.spasm_last_error().decode()
     assert L.spasm_place_round(None, 100, 10, 0, 0, None, 0, dummy, None, None, dummy, None) == -1
 
 

@@ -264,14 +264,20 @@ def test_topm_bit_exact(sp, orc):
 
 
 def test_topm_large_bit_exact(sp, orc):
-    """Chunked top-M beyond one workgroup: ragged tails, ties across chunk borders, and
-    the most rounds (M = 8192 halves the candidates per round)."""
+    """Top-M beyond one workgroup (radix select): ragged last workgroup, ties across
+    workgroup borders, most keys equal to the threshold, NaN keys (sorted last), the
+    largest N and M."""
     rng = np.random.default_rng(702)
-    for n, m in [(16385, 8192), (131072 + 123, 256), (1 << 20, 8192), (40000, 1)]:
+    for n, m, kind in [(16385, 8192, "ties"), (131072 + 123, 256, "ties"), (1 << 20, 8192, "ties"),
+                       (40000, 1, "ties"), (100000, 4096, "zeros"), (70000, 513, "nan"), (16385, 16385 // 2, "zeros")]:
         key = np.round(rng.uniform(0, 1, n), 4).astype(np.float32)  # many ties
+        if kind == "zeros":
+            key[rng.uniform(size=n) < 0.7] = 0.0
+        if kind == "nan":
+            key[rng.uniform(size=n) < 0.1] = np.nan
         idx = N(sp.select_topm_large(T(key), m)).astype(np.int64)
         ref = np.argsort(key.astype(np.float64), kind="stable")[:m]
-        assert np.array_equal(idx, ref), (n, m)
+        assert np.array_equal(idx, ref), (n, m, kind)
     # at or below one workgroup it is the plain selection
     key = np.round(rng.uniform(0, 1, 5000), 3).astype(np.float32)
     assert torch.equal(sp.select_topm_large(T(key), 700), sp.select_topm(T(key), 700))
