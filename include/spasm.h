@@ -215,13 +215,15 @@ int spasm_optimize(spasm_problem prob, int32_t stage, int32_t P, int32_t W, floa
 
 /* --- selection ------------------------------------------------------------------------
  * Alg. 1 ArgSort[:M]: indices of the M smallest keys, ascending, equal keys in index
- * order.  1 <= M <= N <= 16384.  d_key [N], d_idx [M] int32. */
+ * order.  1 <= M <= N <= 16384.  d_key [N], d_idx [M] int32.  Computed by rank: (key,
+ * index) pairs are unique, so each one's sorted position is the count of pairs below it,
+ * counted by up to 256 workgroups at once. */
 int spasm_select_topm(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *stream);
 
 /* The same selection for up to 2^20 keys (M <= 8192 when N > 16384): a radix select
  * (three counting passes over the ordered cost bits find the M-th smallest cost T; the
- * keys below T and the first keys equal to T in index order are collected) followed by a
- * one-workgroup sort of those M keys, so the result equals the stable sort's first M.
+ * keys below T and the first keys equal to T in index order are collected) followed by
+ * the rank selection of those M keys, so the result equals the stable sort's first M.
  * d_work: spasm_select_topm_workspace(N, M) bytes, 256-byte aligned (0 for N <= 16384;
  * d_work may then be NULL). */
 size_t spasm_select_topm_workspace(int32_t N, int32_t M);

@@ -1306,9 +1306,17 @@ __global__ __launch_bounds__(1024) void k_serve(const ServeSolve *solves, int ns
 }
 
 // ------------------------------------------------------------------------------------
-// Selection: one workgroup sorts up to 16384 64-bit keys in LDS (bitonic).
+// Selection (ArgSort of Alg. 1) for up to 16384 unique 64-bit keys, by rank:
 // kind 0 (top-M):  key = ordered(cost) << 32 | index
 // kind 1 (order):  key = unsatisfied << 63 | cost bits << 32 | index   (cost >= 0)
+// kind 2:          keys read from memory (the radix select's survivors)
+// Keys are unique (the index is in them), so the sorted position of a key is the number
+// of keys below it.  Every workgroup builds all n keys in LDS; workgroup g ranks keys
+// [g KB, (g + 1) KB): thread t takes key g KB + (t mod KB) and compares it with one
+// contiguous slice of the n keys; the partial counts are summed (lane shuffles, then
+// LDS) and key i goes to slot rank(i) when that is below nout.  O(n^2) comparisons
+// spread over n / KB workgroups: a few microseconds where one workgroup's sorting network
+// would take tens.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ordered_bits(float f)
 {
@@ -1317,100 +1325,54 @@ __device__ __forceinline__ uint32_t ordered_bits(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ __launch_bounds__(1024) void k_sort(int kind, int n, const float *cost, const float *viol, float eps,
-                                               int M, int32_t *out_idx, int32_t *out_count, const int *skip)
+__global__ __launch_bounds__(1024) void k_rank_sort(int kind, int n, int kb_log2, const float *cost, const float *viol,
+                                                    float eps, const unsigned long long *in_keys, int nout,
+                                                    int32_t *out_idx, int32_t *out_count, const int *skip)
 {
-    extern __shared__ unsigned long long s_keys[];
+    extern __shared__ unsigned long long s_keys[];  // n keys, then 16 x 64 partial counts
     __shared__ int s_cnt;
     if (skip && *skip) return;
-    const int tid = threadIdx.x;
-    int npow = 1;
-    while (npow < n) npow <<= 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int KB = 1 << kb_log2, NS = 1024 >> kb_log2;
     if (tid == 0) s_cnt = 0;
     int cnt = 0;
-    for (int i = tid; i < npow; i += blockDim.x) {
-        unsigned long long key = ~0ull;
-        if (i < n) {
-            if (kind == 0) {
-                key = ((unsigned long long)ordered_bits(cost[i]) << 32) | (unsigned)i;
-            } else {
-                float c = cost[i];
-                if (c != c) c = __int_as_float(0x7f800000);
-                c = fmaxf(c, 0.f);
-                const bool unsat = !(viol[i] < eps);
-                cnt += !unsat;
-                key = ((unsigned long long)unsat << 63) | ((unsigned long long)(__float_as_uint(c) & 0x7fffffffu) << 32) |
-                      (unsigned)i;
-            }
+    for (int i = tid; i < n; i += 1024) {
+        unsigned long long key;
+        if (kind == 0) {
+            key = ((unsigned long long)ordered_bits(cost[i]) << 32) | (unsigned)i;
+        } else if (kind == 1) {
+            float c = cost[i];
+            if (c != c) c = __int_as_float(0x7f800000);
+            c = fmaxf(c, 0.f);
+            const bool unsat = !(viol[i] < eps);
+            cnt += !unsat;
+            key = ((unsigned long long)unsat << 63) | ((unsigned long long)(__float_as_uint(c) & 0x7fffffffu) << 32) |
+                  (unsigned)i;
+        } else {
+            key = in_keys[i];
         }
         s_keys[i] = key;
     }
-    __syncthreads();
+    __syncthreads();  // keys are in; s_cnt is cleared
+    const int kb = tid & (KB - 1), sl = tid >> kb_log2;
+    const int i = blockIdx.x * KB + kb;
+    const unsigned long long ki = i < n ? s_keys[i] : ~0ull;
+    const int len = (n + NS - 1) / NS, j0 = sl * len, j1 = min(n, j0 + len);
+    uint32_t r = 0;
+#pragma unroll 8
+    for (int j = j0; j < j1; ++j) r += s_keys[j] < ki ? 1u : 0u;
+    for (int d = KB; d < 64; d <<= 1) r += __shfl_xor(r, d, 64);
+    uint32_t *s_part = (uint32_t *)(s_keys + n);
+    if (lane < KB) s_part[wave * 64 + lane] = r;
     if (cnt) atomicAdd(&s_cnt, cnt);
-    for (int k = 2; k <= npow; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < npow; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long x = s_keys[i], y = s_keys[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        s_keys[i] = y;
-                        s_keys[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const int nout = kind == 0 ? M : n;
-    for (int i = tid; i < nout; i += blockDim.x) out_idx[i] = (int32_t)(s_keys[i] & 0xffffffffu);
-    if (tid == 0 && out_count) *out_count = kind == 0 ? M : s_cnt;
-}
-
-// Chunked top-M for more keys than one workgroup sorts: workgroup g sorts the keys of
-// its chunk [g chunk, min(n, (g + 1) chunk)) -- built from cost and index in the first
-// round, read from in_keys later -- and keeps its min(M, len) smallest, to out_keys at
-// g M (rounds before the last) or as indices to out_idx (last round, one workgroup).
-// Keys are unique (cost bits, index), so the M smallest kept keys are the M smallest of
-// all, in the same order as one sort of everything.
-__global__ __launch_bounds__(1024) void k_topm_round(int n, const float *cost, const unsigned long long *in_keys,
-                                                     int chunk, int M, unsigned long long *out_keys, int32_t *out_idx)
-{
-    extern __shared__ unsigned long long s_keys[];
-    const int tid = threadIdx.x, lo = blockIdx.x * chunk, len = min(chunk, n - lo);
-    int npow = 1;
-    while (npow < len) npow <<= 1;
-    for (int i = tid; i < npow; i += blockDim.x) {
-        unsigned long long key = ~0ull;
-        if (i < len)
-            key = in_keys ? in_keys[lo + i]
-                          : ((unsigned long long)ordered_bits(cost[lo + i]) << 32) | (unsigned)(lo + i);
-        s_keys[i] = key;
-    }
     __syncthreads();
-    for (int k = 2; k <= npow; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < npow; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long x = s_keys[i], y = s_keys[ixj];
-                    if ((x > y) == ((i & k) == 0)) {
-                        s_keys[i] = y;
-                        s_keys[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    if (tid < KB && i < n) {
+        uint32_t rank = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) rank += s_part[w * 64 + tid];
+        if (rank < (uint32_t)nout) out_idx[rank] = (int32_t)(ki & 0xffffffffu);
     }
-    const int m = min(M, len);
-    for (int i = tid; i < m; i += blockDim.x) {
-        if (out_idx)
-            out_idx[i] = (int32_t)(s_keys[i] & 0xffffffffu);
-        else
-            out_keys[(size_t)blockIdx.x * M + i] = s_keys[i];
-    }
+    if (out_count && blockIdx.x == 0 && tid == 0) *out_count = kind == 1 ? s_cnt : nout;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1429,7 +1391,7 @@ __device__ __forceinline__ void rs_digit(int pass, int &shift, int &bins)
     bins = pass == 2 ? 1024 : 2048;
 }
 
-__global__ __launch_bounds__(1024) void k_rs_init(int M, uint32_t *state, uint32_t *hist, uint32_t *counter)
+__global__ __launch_bounds__(1024) void k_rs_init(int M, uint32_t *state, uint32_t *hist)
 {
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -1437,7 +1399,6 @@ __global__ __launch_bounds__(1024) void k_rs_init(int M, uint32_t *state, uint32
         state[1] = 0;  // mask of those bits
         state[2] = (uint32_t)M;  // keys still needed among those matching the prefix
         state[3] = 0;  // keys known to lie below T
-        *counter = 0;
     }
     for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
 }
@@ -1504,44 +1465,62 @@ __global__ __launch_bounds__(1024) void k_rs_pick(int pass, uint32_t *state, uin
     if (2 * tid + 1 < 2048) hist[2 * tid + 1] = 0;
 }
 
-// keys equal to T per workgroup range
-__global__ __launch_bounds__(1024) void k_rs_eqcount(int n, const float *cost, const uint32_t *state, uint32_t *wg_eq)
+// Keys below T and keys equal to T per workgroup range.
+__global__ __launch_bounds__(1024) void k_rs_count(int n, const float *cost, const uint32_t *state, uint32_t *wg_lt,
+                                                   uint32_t *wg_eq)
 {
-    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_l[16], s_e[16];
     const uint32_t T = state[0];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = blockIdx.x * RS_KEYS, hi = min(n, lo + RS_KEYS);
-    uint32_t c = 0;
-    for (int e = lo + tid; e < hi; e += blockDim.x) c += ordered_bits(cost[e]) == T ? 1u : 0u;
+    uint32_t cl = 0, ce = 0;
+    for (int e = lo + tid; e < hi; e += blockDim.x) {
+        const uint32_t u = ordered_bits(cost[e]);
+        cl += u < T ? 1u : 0u;
+        ce += u == T ? 1u : 0u;
+    }
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    if (lane == 0) s_w[wave] = c;
+    for (int d = 32; d > 0; d >>= 1) {
+        cl += __shfl_xor(cl, d, 64);
+        ce += __shfl_xor(ce, d, 64);
+    }
+    if (lane == 0) {
+        s_l[wave] = cl;
+        s_e[wave] = ce;
+    }
     __syncthreads();
     if (tid == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_w[w];
-        wg_eq[blockIdx.x] = t;
+        uint32_t tl = 0, te = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            tl += s_l[w];
+            te += s_e[w];
+        }
+        wg_lt[blockIdx.x] = tl;
+        wg_eq[blockIdx.x] = te;
     }
 }
 
-// Collect the M keys: every key below T, and the keys equal to T while their rank in
-// index order (over the whole input) is below need.
+// Collect the M keys without atomics: keys below T go to slots in index order (this
+// workgroup's base is the count below T in the ranges before it), then the keys equal to
+// T, after all keys below T, while their rank in index order is below need.
 __global__ __launch_bounds__(1024) void k_rs_collect(int n, const float *cost, const uint32_t *state,
-                                                     const uint32_t *wg_eq, int M, uint32_t *counter,
+                                                     const uint32_t *wg_lt, const uint32_t *wg_eq, int M,
                                                      unsigned long long *surv)
 {
-    __shared__ uint32_t s_w[16];
-    __shared__ uint32_t s_base;
-    const uint32_t T = state[0], need = state[2];
+    __shared__ uint32_t s_l[16], s_e[16];
+    __shared__ uint32_t s_base[2];
+    const uint32_t T = state[0], need = state[2], below = state[3];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    if (tid == 0) {
+    if (tid < 2) {
+        const uint32_t *c = tid == 0 ? wg_lt : wg_eq;
         uint32_t b = 0;
-        for (int g = 0; g < (int)blockIdx.x; ++g) b += wg_eq[g];
-        s_base = b;
+        for (int g = 0; g < (int)blockIdx.x; ++g) b += c[g];
+        s_base[tid] = b;
     }
     __syncthreads();
-    uint32_t run = s_base;
+    uint32_t run_l = s_base[0], run_e = s_base[1];
     const int lo = blockIdx.x * RS_KEYS, hi = min(n, lo + RS_KEYS);
+    const unsigned long long below_lane = (1ull << lane) - 1ull;
     for (int e0 = lo; e0 < hi; e0 += blockDim.x) {
         const int e = e0 + tid;
         uint32_t u = 0;
@@ -1552,26 +1531,34 @@ __global__ __launch_bounds__(1024) void k_rs_collect(int n, const float *cost, c
             eq = u == T;
         }
         const unsigned long long key = ((unsigned long long)u << 32) | (uint32_t)e;
-        if (lt) {
-            const uint32_t slot = atomicAdd(counter, 1u);
-            if (slot < (uint32_t)M) surv[slot] = key;
+        const unsigned long long bl = __ballot(lt), be = __ballot(eq);
+        if (lane == 0) {
+            s_l[wave] = (uint32_t)__popcll(bl);
+            s_e[wave] = (uint32_t)__popcll(be);
         }
-        const unsigned long long bm = __ballot(eq);
-        const uint32_t in_wave = (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
-        if (lane == 0) s_w[wave] = (uint32_t)__popcll(bm);
         __syncthreads();
-        uint32_t before = 0, total = 0;
+        uint32_t before_l = 0, before_e = 0, total_l = 0, total_e = 0;
         for (int w = 0; w < nwave; ++w) {
-            const uint32_t c = s_w[w];
-            if (w < wave) before += c;
-            total += c;
+            const uint32_t cl = s_l[w], ce = s_e[w];
+            if (w < wave) {
+                before_l += cl;
+                before_e += ce;
+            }
+            total_l += cl;
+            total_e += ce;
         }
-        if (eq && run + before + in_wave < need) {
-            const uint32_t slot = atomicAdd(counter, 1u);
+        // slots stay below M by construction (below + need = M); the checks only guard it
+        if (lt) {
+            const uint32_t slot = run_l + before_l + (uint32_t)__popcll(bl & below_lane);
             if (slot < (uint32_t)M) surv[slot] = key;
         }
-        run += total;
-        __syncthreads();  // s_w is rewritten next round
+        if (eq) {
+            const uint32_t r = run_e + before_e + (uint32_t)__popcll(be & below_lane);
+            if (r < need && below + r < (uint32_t)M) surv[below + r] = key;
+        }
+        run_l += total_l;
+        run_e += total_e;
+        __syncthreads();  // s_l and s_e are rewritten next round
     }
 }
 
@@ -2122,9 +2109,8 @@ hipError_t launch_serve(int chunk, int threads, int nwg, const ServeSolve *d_sol
 
 hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_topm_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
+    hipError_t e = hipFuncSetAttribute((const void *)k_rank_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sort_bytes + 16 * 64 * sizeof(uint32_t)));
     if (e != hipSuccess) return e;
 #define SPASM_TRAJ_ATTR(CH)                                                                                      \
     e = hipFuncSetAttribute((const void *)k_traj<2, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
@@ -2139,25 +2125,36 @@ hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
     return hipSuccess;
 }
 
+// Rank selection over n <= 16384 keys: KB keys per workgroup (16, 32 or 64, so that up
+// to 256 workgroups share the work); the first nout sorted indices are written.
+static hipError_t launch_sort(int kind, int n, const float *cost, const float *viol, float eps,
+                              const unsigned long long *in_keys, int nout, int32_t *out_idx, int32_t *out_count,
+                              const int *skip, hipStream_t st)
+{
+    if (n < 1 || n > MAX_SORT || nout > n) return hipErrorInvalidValue;
+    const int kb_log2 = n <= 4096 ? 4 : n <= 8192 ? 5 : 6;
+    const int grid = (n + (1 << kb_log2) - 1) >> kb_log2;
+    const size_t shm = (size_t)n * sizeof(unsigned long long) + 16 * 64 * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_rank_sort, dim3(grid), dim3(1024), shm, st, kind, n, kb_log2, cost, viol, eps, in_keys, nout,
+                       out_idx, out_count, skip);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort_keys(int kind, int n, const float *cost, const float *viol, float eps, int M,
                             int32_t *out_idx, int32_t *out_count, const int *skip, hipStream_t st)
 {
-    int npow = 1;
-    while (npow < n) npow <<= 1;
-    const size_t shm = (size_t)npow * sizeof(unsigned long long);
-    hipLaunchKernelGGL(k_sort, dim3(1), dim3(1024), shm, st, kind, n, cost, viol, eps, M, out_idx, out_count, skip);
-    return hipGetLastError();
+    return launch_sort(kind, n, cost, viol, eps, nullptr, kind == 0 ? M : n, out_idx, out_count, skip, st);
 }
 
 static size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace of the radix select: state (4 words) and counter in the first 256 bytes, the
-// 2048-bin histogram, the per-workgroup counts of keys equal to T, then M 64-bit keys.
+// Workspace of the radix select: state (4 words) in the first 256 bytes, the 2048-bin
+// histogram, the per-workgroup counts of keys below and equal to T, then M 64-bit keys.
 size_t topm_workspace(int n, int M)
 {
     if (n <= MAX_SORT) return 0;
     const size_t G = (size_t)(n + RS_KEYS - 1) / RS_KEYS;
-    return 256 + 2048 * sizeof(uint32_t) + align_up256(G * sizeof(uint32_t)) + (size_t)M * sizeof(unsigned long long);
+    return 256 + 2048 * sizeof(uint32_t) + align_up256(2 * G * sizeof(uint32_t)) + (size_t)M * sizeof(unsigned long long);
 }
 
 hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *ws, hipStream_t st)
@@ -2165,25 +2162,20 @@ hipError_t launch_topm(int n, const float *cost, int M, int32_t *out_idx, void *
     if (n <= MAX_SORT) return launch_sort_keys(0, n, cost, nullptr, 0.f, M, out_idx, nullptr, nullptr, st);
     const int G = (n + RS_KEYS - 1) / RS_KEYS;
     char *w = (char *)ws;
-    uint32_t *state = (uint32_t *)w, *counter = state + 8;
+    uint32_t *state = (uint32_t *)w;
     uint32_t *hist = (uint32_t *)(w + 256);
-    uint32_t *wg_eq = (uint32_t *)(w + 256 + 2048 * sizeof(uint32_t));
+    uint32_t *wg_lt = (uint32_t *)(w + 256 + 2048 * sizeof(uint32_t)), *wg_eq = wg_lt + G;
     unsigned long long *surv =
-        (unsigned long long *)(w + 256 + 2048 * sizeof(uint32_t) + align_up256((size_t)G * sizeof(uint32_t)));
-    hipLaunchKernelGGL(k_rs_init, dim3(1), dim3(1024), 0, st, M, state, hist, counter);
+        (unsigned long long *)(w + 256 + 2048 * sizeof(uint32_t) + align_up256(2 * (size_t)G * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_rs_init, dim3(1), dim3(1024), 0, st, M, state, hist);
     for (int pass = 0; pass < 3; ++pass) {
         hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(1024), 0, st, n, cost, pass, (const uint32_t *)state, hist);
         hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(1024), 0, st, pass, state, hist);
     }
-    hipLaunchKernelGGL(k_rs_eqcount, dim3(G), dim3(1024), 0, st, n, cost, (const uint32_t *)state, wg_eq);
+    hipLaunchKernelGGL(k_rs_count, dim3(G), dim3(1024), 0, st, n, cost, (const uint32_t *)state, wg_lt, wg_eq);
     hipLaunchKernelGGL(k_rs_collect, dim3(G), dim3(1024), 0, st, n, cost, (const uint32_t *)state,
-                       (const uint32_t *)wg_eq, M, counter, surv);
-    int npow = 1;
-    while (npow < M) npow <<= 1;
-    hipLaunchKernelGGL(k_topm_round, dim3(1), dim3(1024), (size_t)npow * sizeof(unsigned long long), st, M,
-                       (const float *)nullptr, (const unsigned long long *)surv, M, M, (unsigned long long *)nullptr,
-                       out_idx);
-    return hipGetLastError();
+                       (const uint32_t *)wg_lt, (const uint32_t *)wg_eq, M, surv);
+    return launch_sort(2, M, nullptr, nullptr, 0.f, surv, M, out_idx, nullptr, nullptr, st);
 }
 
 hipError_t launch_gather_place(int B, int M, const float *xs, const float *cs, const float *vs, const int32_t *ord,

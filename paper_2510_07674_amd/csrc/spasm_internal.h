@@ -13,8 +13,8 @@ constexpr int NJ = 7;           // joints of the serial chain
 constexpr int MAX_B = 16;       // blocks per problem
 constexpr int MAX_THREADS = 1024;
 constexpr int MAX_SORT = 16384; // single-workgroup sort capacity (LDS bound)
-constexpr int MAX_TOPM_N = 1 << 20;  // chunked top-M: keys
-constexpr int MAX_TOPM_M = MAX_SORT / 2;  // chunked top-M: kept per chunk (each round halves at least)
+constexpr int MAX_TOPM_N = 1 << 20;  // radix-select top-M: keys
+constexpr int MAX_TOPM_M = MAX_SORT / 2;  // radix-select top-M: selected keys
 
 // Problem constants passed BY VALUE to every kernel: they land in the kernel-argument
 // segment and are read into scalar registers, so every lane of a wave shares one copy.

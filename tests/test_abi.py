@@ -138,14 +138,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 
 def test_topm_and_place_shapes():
-    """Chunked selection and placement-round shape checks run on the host."""
+    """Radix-select workspace sizes and placement-round shape checks run on the host."""
     from paper_2510_07674_amd import spasm
     L = spasm.load()
     assert L.spasm_select_topm_workspace(16384, 2048) == 0
-    # radix select: state (256 B), 2048-bin histogram, per-workgroup counts of 4096 keys
-    # rounded up to 256 B, M (cost bits, index) survivors
+    # radix select: state (256 B), 2048-bin histogram, two counts per workgroup of 4096
+    # keys rounded up to 256 B, M (cost bits, index) survivors
     assert L.spasm_select_topm_workspace(131072, 256) == 256 + 2048 * 4 + 256 + 256 * 8
-    assert L.spasm_select_topm_workspace(1 << 20, 8192) == 256 + 2048 * 4 + 1024 + 8192 * 8
+    assert L.spasm_select_topm_workspace(1 << 20, 8192) == 256 + 2048 * 4 + 2048 + 8192 * 8
     assert L.spasm_select_topm_workspace(1 << 21, 256) == 0          # too many keys
     assert L.spasm_select_topm_workspace(20000, 8193) == 0           # M too large for chunking
     dummy = ctypes.c_void_p(256)

@@ -256,7 +256,9 @@ def test_autograd_matches_finite_differences(sp, orc):
 # ---------------------------------------------------------------- selection
 def test_topm_bit_exact(sp, orc):
     rng = np.random.default_rng(700)
-    for n, m in [(16384, 2048), (4096, 1024), (1000, 999), (1, 1), (3000, 7)]:
+    # every register width of the sort: 1024 E slots for E = 1, 2, 4, 8, 16
+    for n, m in [(16384, 2048), (4096, 1024), (1000, 999), (1, 1), (3000, 7), (1025, 1025), (2049, 300),
+                 (8000, 5000), (12345, 1), (64, 3)]:
         key = np.round(rng.uniform(0, 1, n), 3).astype(np.float32)  # many ties
         idx = N(sp.select_topm(T(key), m)).astype(np.int64)
         ref = orc.Oracle.argsort(key.astype(np.float64))[:m]
@@ -305,7 +307,7 @@ def test_order_bit_exact(sp, orc):
     rng = np.random.default_rng(701)
     prob, pr, _ = synth.config("tower4", 0)
     o = orc.Oracle(prob, pr)
-    for n in (2048, 1024, 37, 16384):
+    for n in (2048, 1024, 37, 16384, 1025, 5000, 9000):
         cost = np.round(rng.uniform(0, 1, n), 3).astype(np.float32)
         viol = np.where(rng.uniform(size=n) < 0.3, 0, rng.uniform(0, 2e-3, n)).astype(np.float32)
         out, ns = sp.order(T(cost), T(viol), pr.sat_eps)
