@@ -263,6 +263,14 @@ __device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (
     return b;
 }
 
+// Narrow-phase passes (sphere chunks tested exactly against one box) of each wave in the
+// current stage-2 iteration.  A particle's waves meet at barriers every iteration, so the
+// wave with the most contacts sets its particle's pace, and the launch ends with the
+// slowest particle; that wave takes a higher issue priority on its SIMD for the next
+// iteration (see traj_particle).
+__shared__ int s_wave_work[16];
+constexpr int PRIO_STEP = 48;  // narrow-phase passes per priority level (levels 0..3)
+
 template <bool GRAD, int CH>
 __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
                                               const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
@@ -272,6 +280,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
     const float lo0 = uniform(wave_min(lb.lo0)), lo1 = uniform(wave_min(lb.lo1)), lo2 = uniform(wave_min(lb.lo2));
     const float hi0 = uniform(wave_max(lb.hi0)), hi1 = uniform(wave_max(lb.hi1)), hi2 = uniform(wave_max(lb.hi2));
     const int lane = threadIdx.x & 63;
+    int nar = 0;  // wave-uniform
     for (int base = 0; base < P.O; base += 64) {
         const int ol = base + lane;
         bool ov = false;
@@ -304,6 +313,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 if (!hm[i]) continue;
+                ++nar;
                 const float dx = cx[i] - bc.x, dy = cy[i] - bc.y, dz = cz[i] - bc.z;
                 const float ux = fabsf(dx) - be.x, uy = fabsf(dy) - be.y, uz = fabsf(dz) - be.z;
                 float gx, gy, gz;
@@ -313,6 +323,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
             }
         }
     }
+    if (nar && lane == 0) s_wave_work[threadIdx.x >> 6] += nar;
 }
 
 // Blocks as they stand while the lane's segment runs: b' < b at the placement variable
@@ -1140,9 +1151,25 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     }
     __syncthreads();
 
+    if (lane == 0) s_wave_work[wave] = 0;
     if (MODE == 2) {
         const float b1 = P.beta1, b2 = P.beta2, eps = P.adam_eps;
         for (int k = a.k_begin; k < a.k_end; ++k) {
+            {
+                // issue priority from the previous iteration's contact work: the waves
+                // that hold their particles back run first on their SIMDs (scheduling
+                // only; the arithmetic is the same)
+                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / PRIO_STEP;
+                if (lane == 0) s_wave_work[wave] = 0;
+                if (lvl >= 3)
+                    __builtin_amdgcn_s_setprio(3);
+                else if (lvl == 2)
+                    __builtin_amdgcn_s_setprio(2);
+                else if (lvl == 1)
+                    __builtin_amdgcn_s_setprio(1);
+                else
+                    __builtin_amdgcn_s_setprio(0);
+            }
             int phase;
             float lr;
             schedule(k, a.k_lin2, P.eta2, P.alpha2, phase, lr);
