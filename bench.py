@@ -32,9 +32,10 @@ def flop_per_eval(S, O, B, W):
     return 505 + 18 * S + 9 * S * O + 18 * S * b_vis + f_tr * (144 + 72 * (O + B - 1)) + 450
 
 
-def stored_traffic():
+def stored_traffic(workload):
     """HBM bytes per launch of the fused stage-2 kernel from the committed counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+    or None when the kernel source has changed since the counters were taken or the
+    workload is not the one they were taken on."""
     import hashlib
     summary = os.path.join(ROOT, "profiles", "k_traj_tower4_counters.md")
     src = os.path.join(ROOT, "paper_2510_07674_amd", "csrc", "kernels.hip")
@@ -48,7 +49,7 @@ def stored_traffic():
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if fields.get("kernels_sha256") != sha:
+    if fields.get("kernels_sha256") != sha or fields.get("workload") != workload:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -170,7 +171,7 @@ def main():
         "success_rate": float(np.mean([r["success"] for r in results])),
         "roofline": {"bound": "alu", "kernel": "k_traj<2> (fused stage-2 cost+grad+Adam)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": stored_traffic(), "avg_ms": opt_ms},
+                     "frac": achieved / PEAK_FP32, "traffic": stored_traffic(args.workload), "avg_ms": opt_ms},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
