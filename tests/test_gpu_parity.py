@@ -223,13 +223,15 @@ def test_adjoint_is_scaled_gradient(sp):
     assert torch.equal(ap, gp * gout.view(16, 1, 1))
 
 
-def test_autograd_matches_finite_differences(sp, orc):
+@pytest.mark.parametrize("W", [4, 32])
+def test_autograd_matches_finite_differences(sp, orc, W):
     """SpasmCost backward against central differences of the FP64 oracle cost along
-    random directions (h = 1e-6), on 256 particles of the 4-block tower."""
+    random directions (h = 1e-6), on 256 particles of the 4-block tower (W = 32: the
+    65,536 particle-waypoint batch)."""
     rng = np.random.default_rng(600)
     prob, pr, _ = synth.config("tower4", 5)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
-    P, W = 256, 4
+    P = 256
     q, pose = synth.random_states(rng, prob, P, W)
     q, pose = f32(q), f32(pose)
     tq = T(q).requires_grad_(True)
