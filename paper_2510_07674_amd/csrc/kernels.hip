@@ -663,18 +663,21 @@ __global__ void k_sample(KProb P, int N, uint64_t seed, int round, float *x, con
     }
 }
 
-// One workgroup holds lcm(8B, 64) lanes = several particles; lane = (particle, block,
-// sphere).  Steps k_begin..k_end-1 of descent (clamped to the region), then one
-// evaluation at eval_phase.
+// One workgroup holds lcm(L B, 64) lanes = several particles, L = 2^lpb_log2 lanes per
+// block (8 block spheres; for packing, the cells of the largest piece rounded up to a
+// power of two); lane = (particle, block, sphere or cell).  Steps k_begin..k_end-1 of
+// descent (clamped to the region), then one evaluation at eval_phase.  Dynamic LDS:
+// per particle and block 8 floats of state and 2 of reduction.
 __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_in, const int32_t *idx,
                                                 float *x_out, int k_begin, int k_end, int eval_phase,
                                                 float *cost_out, float *viol_out, float *gx_out, const int *skip)
 {
-    __shared__ float s_state[128 * 8];  // [particles per WG * B][8]
-    __shared__ float s_red[128][2];
+    extern __shared__ float s_place[];
     if (skip && *skip) return;
-    const int B = P.B, per = 8 * B, ppw = blockDim.x / per;
-    const int tid = threadIdx.x, lp = tid / per, rem = tid % per, i = rem >> 3, k = rem & 7;
+    const int B = P.B, lg = P.lpb_log2, L = 1 << lg, per = L * B, ppw = blockDim.x / per;
+    const int tid = threadIdx.x, lp = tid / per, rem = tid % per, i = rem >> lg, k = rem & (L - 1);
+    float *s_state = s_place;                                    // [ppw * B][8]
+    float(*s_red)[2] = (float(*)[2])(s_place + ppw * B * 8);     // [ppw * B][2]
     const int p = blockIdx.x * ppw + lp;
     const bool valid = p < n;
     float *st = s_state + lp * B * 8;
@@ -703,8 +706,7 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
         schedule(kk, P.k_lin1, P.eta1, P.alpha1, phase, lr);
         float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
         stage1_lane<true>(P, phase, i, k, st, c, v, g);
-#pragma unroll
-        for (int m = 1; m < 8; m <<= 1) {
+        for (int m = 1; m < L; m <<= 1) {
             g[0] += __shfl_xor(g[0], m, 64);
             g[1] += __shfl_xor(g[1], m, 64);
             g[3] += __shfl_xor(g[3], m, 64);
@@ -729,8 +731,7 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
         stage1_lane<true>(P, eval_phase, i, k, st, c, v, g);
     else
         stage1_lane<false>(P, eval_phase, i, k, st, c, v, g);
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
+    for (int m = 1; m < L; m <<= 1) {
         c += __shfl_xor(c, m, 64);
         v = fmaxf(v, __shfl_xor(v, m, 64));
         g[0] += __shfl_xor(g[0], m, 64);
@@ -2087,8 +2088,9 @@ hipError_t launch_sample(const KProb &P, int N, uint64_t seed, int round, float 
 hipError_t launch_place(const KProb &P, int n, const float *x_in, const int32_t *idx, float *x_out, int k_begin,
                         int k_end, int eval_phase, float *cost, float *viol, float *gx, const int *skip, hipStream_t st)
 {
-    const int per = 8 * P.B, threads = lcm_int(per, 64), ppw = threads / per;
-    hipLaunchKernelGGL(k_place, dim3((n + ppw - 1) / ppw), dim3(threads), 0, st, P, n, x_in, idx, x_out, k_begin,
+    const int per = P.B << P.lpb_log2, threads = lcm_int(per, 64), ppw = threads / per;
+    const size_t shm = (size_t)ppw * P.B * 10 * sizeof(float);
+    hipLaunchKernelGGL(k_place, dim3((n + ppw - 1) / ppw), dim3(threads), shm, st, P, n, x_in, idx, x_out, k_begin,
                        k_end, eval_phase, cost, viol, gx, skip);
     return hipGetLastError();
 }
