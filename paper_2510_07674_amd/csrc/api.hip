@@ -273,10 +273,10 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.cells = (const float4 *)(base + off_cells);
     K.yaw_steps = skel->sample_yaw_steps;
     K.lpb_log2 = 3;
-    if (skel->mode == SPASM_MODE_PACK) {  // one lane per cell of the largest piece
+    if (skel->mode == SPASM_MODE_PACK) {  // one lane per cell of the largest piece, at least 4
         int mc = 1;
         for (int b = 0; b < B; ++b) mc = std::max(mc, (int)skel->pack_cells[b]);
-        K.lpb_log2 = mc <= 1 ? 0 : mc <= 2 ? 1 : mc <= 4 ? 2 : 3;
+        K.lpb_log2 = mc <= 4 ? 2 : 3;
     }
     K.al_every = prm->al_every;
     K.al_rho = (float)prm->al_rho;

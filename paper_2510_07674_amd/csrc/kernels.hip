@@ -538,19 +538,21 @@ __device__ __forceinline__ void place_lane(const KProb &P, int phase, int i, int
     }
 }
 
-// Packing placement cost (Appendix A, Tetris problem) of cell k of piece i: the cell
-// against the four walls of the region and against every cell of the other pieces.
-// Cells are squares of half edge s that share their piece's yaw.  For two of them with
-// relative yaw D and centre offset d, the projected half extents along any of the four
-// edge normals n sum to s (1 + |cos D| + |sin D|), so the separating-axis depth is that
-// sum minus the largest |d.n|.  A pair's cost is taken by the lane of the lower-numbered
-// piece; every lane adds the gradient of all of its pairs with respect to its own piece,
-// so no lane writes another's gradient.  Lanes past the piece's last cell only hold the
-// height term (lane 0).
+// Packing placement cost of a whole particle, each cell pair evaluated once.  Lane (i, k)
+// holds cell k of piece i.  Its cell's world centre and yaw derivative go to LDS; piece i
+// then takes the pairs with pieces j = i + t (mod B), t = 1..floor(B/2) (for t = B/2 only
+// when i < j), so every unordered pair of pieces is met once and the pieces share the
+// work evenly.  A pair's cost and both pieces' gradients come from that one evaluation:
+// the gradient with respect to piece j is what j's own lane would compute (its normals
+// first in the choice of the separating axis, d -> -d); it is summed over i's lanes and
+// left in LDS per (i, t), and after a barrier each piece adds the contributions left
+// for it in fixed order of t.  Called by every lane of the workgroup (barriers inside).
 template <bool GRAD>
-__device__ __forceinline__ void pack_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost,
-                                          float &viol, float (&g)[4])
+__device__ __forceinline__ void pack_particle(const KProb &P, int phase, int i, int k, int L, const float *st,
+                                              float4 *s_cell, float *s_gj, float &cost, float &viol,
+                                              float (&g)[4])
 {
+    const int B = P.B, T = B >> 1;
     const float w = P.w[W_COLL], s = P.half;
     if (k == 0) {  // height: zero while z stays on the table
         const float w_h = P.w[W_HEIGHT];
@@ -560,68 +562,119 @@ __device__ __forceinline__ void pack_lane(const KProb &P, int phase, int i, int 
         if (GRAD) g[2] += 2.f * w_h * e;
     }
     const float4 ck = ldc(P.cells, 8 * i + k);
-    if (ck.z == 0.f) return;
+    const bool valid = ck.z != 0.f;
     const float xi = st[i * 8 + 0], yi = st[i * 8 + 1], ci = st[i * 8 + 4], si = st[i * 8 + 5];
     const float ax = xi + ci * ck.x - si * ck.y, ay = yi + si * ck.x + ci * ck.y;
     const float dax = -si * ck.x - ci * ck.y, day = ci * ck.x - si * ck.y;  // d(ax, ay) / d yaw_i
-    // walls: the cell reaches e = s (|cos| + |sin|) from its centre along x and along y
-    const float e = s * (fabsf(ci) + fabsf(si));
-    const float de = s * (sgnf(si) * ci - sgnf(ci) * si);  // d e / d yaw_i
-    const float wd[4] = {P.wall[0] - (ax - e), (ax + e) - P.wall[1], P.wall[2] - (ay - e), (ay + e) - P.wall[3]};
+    // cells past a piece's last one sit far away, so they never overlap anything
+    s_cell[i * L + k] = valid ? make_float4(ax, ay, dax, day) : make_float4(1e30f, 1e30f, 0.f, 0.f);
+    __syncthreads();
+    if (valid) {
+        // walls: the cell reaches e = s (|cos| + |sin|) from its centre along x and along y
+        const float e = s * (fabsf(ci) + fabsf(si));
+        const float de = s * (sgnf(si) * ci - sgnf(ci) * si);  // d e / d yaw_i
+        const float wd[4] = {P.wall[0] - (ax - e), (ax + e) - P.wall[1], P.wall[2] - (ay - e), (ay + e) - P.wall[3]};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (wd[q] > 0.f) {
-            cost += w * phi(phase, wd[q]);
-            viol = fmaxf(viol, wd[q]);
-            if (GRAD) {
-                const float sc = w * dphi(phase, wd[q]);
-                const float sgn = (q & 1) ? 1.f : -1.f;  // inward side: -1 for x_lo / y_lo
-                if (q < 2) {
-                    g[0] += sc * sgn;
-                    g[3] += sc * (sgn * dax + de);
-                } else {
-                    g[1] += sc * sgn;
-                    g[3] += sc * (sgn * day + de);
+        for (int q = 0; q < 4; ++q) {
+            if (wd[q] > 0.f) {
+                cost += w * phi(phase, wd[q]);
+                viol = fmaxf(viol, wd[q]);
+                if (GRAD) {
+                    const float sc = w * dphi(phase, wd[q]);
+                    const float sgn = (q & 1) ? 1.f : -1.f;  // inward side: -1 for x_lo / y_lo
+                    if (q < 2) {
+                        g[0] += sc * sgn;
+                        g[3] += sc * (sgn * dax + de);
+                    } else {
+                        g[1] += sc * sgn;
+                        g[3] += sc * (sgn * day + de);
+                    }
                 }
             }
         }
     }
-    for (int j = 0; j < P.B; ++j) {
-        if (j == i) continue;
-        const float xj = st[j * 8 + 0], yj = st[j * 8 + 1], cj = st[j * 8 + 4], sj = st[j * 8 + 5];
+    for (int t = 1; t <= T; ++t) {
+        int j = i + t;
+        if (j >= B) j -= B;
+        const bool take = valid && (2 * t < B || i < j);
+        const float cj = st[j * 8 + 4], sj = st[j * 8 + 5];
         const float cD = cj * ci + sj * si, sD = sj * ci - cj * si;  // cos, sin of yaw_j - yaw_i
         const float R = s * (1.f + fabsf(cD) + fabsf(sD));
-        const float dR = s * (sgnf(cD) * sD - sgnf(sD) * cD);  // d R / d yaw_i
-        for (int m = 0; m < 8; ++m) {
-            const float4 cm = ldc(P.cells, 8 * j + m);
-            if (cm.z == 0.f) break;  // a piece's cells come first
-            const float bx = xj + cj * cm.x - sj * cm.y, by = yj + sj * cm.x + cj * cm.y;
-            const float dx = ax - bx, dy = ay - by;
+        const float dR = s * (sgnf(cD) * sD - sgnf(sD) * cD);      // d R / d yaw_i
+        const float dRj = s * (sgnf(cD) * -sD - sgnf(-sD) * cD);   // d R / d yaw_j
+        float h0 = 0.f, h1 = 0.f, h3 = 0.f;  // gradient with respect to piece j
+        for (int m = 0; m < L; ++m) {
+            const float4 cb = s_cell[j * L + m];
+            const float dx = ax - cb.x, dy = ay - cb.y;
             // projections of d on the normals (cos_i, sin_i), (-sin_i, cos_i), then piece j's
             const float p0 = dx * ci + dy * si, p1 = dy * ci - dx * si;
             const float p2 = dx * cj + dy * sj, p3 = dy * cj - dx * sj;
-            int best = 0;  // the first largest |projection| (the oracle's first smallest overlap)
-            float mx = fabsf(p0);
-            if (fabsf(p1) > mx) { mx = fabsf(p1); best = 1; }
-            if (fabsf(p2) > mx) { mx = fabsf(p2); best = 2; }
-            if (fabsf(p3) > mx) { mx = fabsf(p3); best = 3; }
+            const float a0 = fabsf(p0), a1 = fabsf(p1), a2 = fabsf(p2), a3 = fabsf(p3);
+            const float mx = fmaxf(fmaxf(a0, a1), fmaxf(a2, a3));
             const float pen = R - mx;
-            if (pen <= 0.f) continue;
-            if (j > i) {
-                cost += w * phi(phase, pen);
-                viol = fmaxf(viol, pen);
-            }
+            if (!(take && pen > 0.f)) continue;
+            cost += w * phi(phase, pen);
+            viol = fmaxf(viol, pen);
             if (GRAD) {
-                // pen = R - sg (d.n): n, sg and d.(dn / d yaw_i) for the chosen normal
-                float nx, ny, pc, dn;
-                if (best == 0) { nx = ci; ny = si; pc = p0; dn = p1; }
-                else if (best == 1) { nx = -si; ny = ci; pc = p1; dn = -p0; }
-                else if (best == 2) { nx = cj; ny = sj; pc = p2; dn = 0.f; }
-                else { nx = -sj; ny = cj; pc = p3; dn = 0.f; }
-                const float sc = w * dphi(phase, pen), sg = sgnf(pc);
-                g[0] -= sc * sg * nx;
-                g[1] -= sc * sg * ny;
-                g[3] += sc * (dR - sg * (dax * nx + day * ny + dn));
+                const float sc = w * dphi(phase, pen);
+                {  // piece i: its own normals first (the first largest |projection|)
+                    int best = 0;
+                    float bm = a0;
+                    if (a1 > bm) { bm = a1; best = 1; }
+                    if (a2 > bm) { bm = a2; best = 2; }
+                    if (a3 > bm) { best = 3; }
+                    float nx, ny, pc, dn;
+                    if (best == 0) { nx = ci; ny = si; pc = p0; dn = p1; }
+                    else if (best == 1) { nx = -si; ny = ci; pc = p1; dn = -p0; }
+                    else if (best == 2) { nx = cj; ny = sj; pc = p2; dn = 0.f; }
+                    else { nx = -sj; ny = cj; pc = p3; dn = 0.f; }
+                    const float sg = sgnf(pc);
+                    g[0] -= sc * sg * nx;
+                    g[1] -= sc * sg * ny;
+                    g[3] += sc * (dR - sg * (dax * nx + day * ny + dn));
+                }
+                {  // piece j, as its own lane sees the pair: d -> -d, its normals first
+                    int best = 2;
+                    float bm = a2;
+                    if (a3 > bm) { bm = a3; best = 3; }
+                    if (a0 > bm) { bm = a0; best = 0; }
+                    if (a1 > bm) { best = 1; }
+                    float nx, ny, pc, dn;
+                    if (best == 2) { nx = cj; ny = sj; pc = -p2; dn = -p3; }
+                    else if (best == 3) { nx = -sj; ny = cj; pc = -p3; dn = p2; }
+                    else if (best == 0) { nx = ci; ny = si; pc = -p0; dn = 0.f; }
+                    else { nx = -si; ny = ci; pc = -p1; dn = 0.f; }
+                    const float sg = sgnf(pc);
+                    h0 -= sc * sg * nx;
+                    h1 -= sc * sg * ny;
+                    h3 += sc * (dRj - sg * (cb.z * nx + cb.w * ny + dn));
+                }
+            }
+        }
+        if (GRAD) {
+            for (int d = 1; d < L; d <<= 1) {
+                h0 += __shfl_xor(h0, d, 64);
+                h1 += __shfl_xor(h1, d, 64);
+                h3 += __shfl_xor(h3, d, 64);
+            }
+            if (k == 0) {
+                float *o = s_gj + (i * T + t - 1) * 3;
+                o[0] = h0;
+                o[1] = h1;
+                o[2] = h3;
+            }
+        }
+    }
+    if (GRAD) {
+        __syncthreads();
+        if (k == 0) {
+            for (int t = 1; t <= T; ++t) {
+                int src = i - t;
+                if (src < 0) src += B;
+                const float *o = s_gj + (src * T + t - 1) * 3;
+                g[0] += o[0];
+                g[1] += o[1];
+                g[3] += o[2];
             }
         }
     }
@@ -630,11 +683,11 @@ __device__ __forceinline__ void pack_lane(const KProb &P, int phase, int i, int 
 // Stage-1 placement cost of one lane: the packing cost for packing problems, the tower /
 // fixed-goal cost otherwise (the mode is uniform, so the branch does not diverge).
 template <bool GRAD>
-__device__ __forceinline__ void stage1_lane(const KProb &P, int phase, int i, int k, const float *st, float &cost,
-                                            float &viol, float (&g)[4])
+__device__ __forceinline__ void stage1_lane(const KProb &P, int phase, int i, int k, int L, const float *st,
+                                            float4 *s_cell, float *s_gj, float &cost, float &viol, float (&g)[4])
 {
     if (P.mode == SPASM_MODE_PACK)
-        pack_lane<GRAD>(P, phase, i, k, st, cost, viol, g);
+        pack_particle<GRAD>(P, phase, i, k, L, st, s_cell, s_gj, cost, viol, g);
     else
         place_lane<GRAD>(P, phase, i, k, st, cost, viol, g);
 }
@@ -665,19 +718,26 @@ __global__ void k_sample(KProb P, int N, uint64_t seed, int round, float *x, con
 
 // One workgroup holds lcm(L B, 64) lanes = several particles, L = 2^lpb_log2 lanes per
 // block (8 block spheres; for packing, the cells of the largest piece rounded up to a
-// power of two); lane = (particle, block, sphere or cell).  Steps k_begin..k_end-1 of
+// power of two, at least 4); lane = (particle, block, sphere or cell).  Steps k_begin..k_end-1 of
 // descent (clamped to the region), then one evaluation at eval_phase.  Dynamic LDS:
-// per particle and block 8 floats of state and 2 of reduction.
+// per particle and block 8 floats of state and 2 of reduction (and for packing the cell
+// table and the pair gradients of pack_particle).
 __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_in, const int32_t *idx,
                                                 float *x_out, int k_begin, int k_end, int eval_phase,
                                                 float *cost_out, float *viol_out, float *gx_out, const int *skip)
 {
-    extern __shared__ float s_place[];
+    extern __shared__ float4 s_place4[];
     if (skip && *skip) return;
     const int B = P.B, lg = P.lpb_log2, L = 1 << lg, per = L * B, ppw = blockDim.x / per;
     const int tid = threadIdx.x, lp = tid / per, rem = tid % per, i = rem >> lg, k = rem & (L - 1);
-    float *s_state = s_place;                                    // [ppw * B][8]
-    float(*s_red)[2] = (float(*)[2])(s_place + ppw * B * 8);     // [ppw * B][2]
+    const bool pack = P.mode == SPASM_MODE_PACK;
+    const int T = B >> 1;
+    float4 *s_cell = s_place4;                                     // packing: [ppw][B L] cells
+    float *s_state = (float *)(s_place4 + (pack ? ppw * B * L : 0));  // [ppw * B][8]
+    float(*s_red)[2] = (float(*)[2])(s_state + ppw * B * 8);       // [ppw * B][2]
+    float *s_gj = s_state + ppw * B * 10;                          // packing: [ppw][B][T][3]
+    float4 *cell_p = s_cell + lp * B * L;
+    float *gj_p = s_gj + lp * B * T * 3;
     const int p = blockIdx.x * ppw + lp;
     const bool valid = p < n;
     float *st = s_state + lp * B * 8;
@@ -705,7 +765,7 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
         float lr;
         schedule(kk, P.k_lin1, P.eta1, P.alpha1, phase, lr);
         float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
-        stage1_lane<true>(P, phase, i, k, st, c, v, g);
+        stage1_lane<true>(P, phase, i, k, L, st, cell_p, gj_p, c, v, g);
         for (int m = 1; m < L; m <<= 1) {
             g[0] += __shfl_xor(g[0], m, 64);
             g[1] += __shfl_xor(g[1], m, 64);
@@ -728,9 +788,9 @@ __global__ __launch_bounds__(1024) void k_place(KProb P, int n, const float *x_i
     }
     float c = 0.f, v = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};
     if (gx_out)
-        stage1_lane<true>(P, eval_phase, i, k, st, c, v, g);
+        stage1_lane<true>(P, eval_phase, i, k, L, st, cell_p, gj_p, c, v, g);
     else
-        stage1_lane<false>(P, eval_phase, i, k, st, c, v, g);
+        stage1_lane<false>(P, eval_phase, i, k, L, st, cell_p, gj_p, c, v, g);
     for (int m = 1; m < L; m <<= 1) {
         c += __shfl_xor(c, m, 64);
         v = fmaxf(v, __shfl_xor(v, m, 64));
@@ -2088,8 +2148,11 @@ hipError_t launch_sample(const KProb &P, int N, uint64_t seed, int round, float 
 hipError_t launch_place(const KProb &P, int n, const float *x_in, const int32_t *idx, float *x_out, int k_begin,
                         int k_end, int eval_phase, float *cost, float *viol, float *gx, const int *skip, hipStream_t st)
 {
-    const int per = P.B << P.lpb_log2, threads = lcm_int(per, 64), ppw = threads / per;
-    const size_t shm = (size_t)ppw * P.B * 10 * sizeof(float);
+    const int L = 1 << P.lpb_log2, per = P.B * L, threads = lcm_int(per, 64), ppw = threads / per;
+    // state and reduction per block; packing adds the cells (float4 each) and the pair
+    // gradients left for other pieces (3 floats per piece and offset t = 1..B/2)
+    const bool pack = P.mode == SPASM_MODE_PACK;
+    const size_t shm = (size_t)ppw * P.B * (10 + (pack ? 4 * L + 3 * (P.B / 2) : 0)) * sizeof(float);
     hipLaunchKernelGGL(k_place, dim3((n + ppw - 1) / ppw), dim3(threads), shm, st, P, n, x_in, idx, x_out, k_begin,
                        k_end, eval_phase, cost, viol, gx, skip);
     return hipGetLastError();

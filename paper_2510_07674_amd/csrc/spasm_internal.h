@@ -27,7 +27,7 @@ struct KProb {
     const float4 *cells;     // [B][8] packing cells (ox, oy, 1, 0); (0, 0, 0, 0) past a piece's last cell
     int B, S, O, mode;
     int yaw_steps;           // stage-1 yaw samples on yaw_steps directions (0: uniform)
-    int lpb_log2;            // stage-1 lanes per block: 8 block spheres (3); packing: cells rounded up to 2^k
+    int lpb_log2;            // stage-1 lanes per block: 8 block spheres (3); packing: cells rounded up to 2^k >= 4
     float wall[4];           // packing walls: region x_lo, x_hi, y_lo, y_hi
     float p2p_goal[NJ];      // point-to-point goal configuration (the start is q_home)
     int al_every;            // augmented Lagrangian: multiplier step every al_every iterations (0: off)
