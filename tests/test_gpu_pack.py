@@ -147,12 +147,12 @@ def test_pack_rejects_stage2(sp):
     assert "stage 1 only" in L.spasm_last_error().decode()
 
 
-def _ragged_pieces(rng, base, B):
-    """B pieces of 1..8 distinct cells each (random lattice shapes, not a tiling)."""
+def _ragged_pieces(rng, base, B, max_cells=synth.MAX_CELLS):
+    """B pieces of 1..max_cells distinct cells each (random lattice shapes, not a tiling)."""
     cells = np.zeros(B, np.int32)
     off = np.zeros((B, synth.MAX_CELLS, 2))
     for b in range(B):
-        n = int(rng.integers(1, synth.MAX_CELLS + 1))
+        n = int(rng.integers(1, max_cells + 1))
         pick = rng.choice(16, n, replace=False)
         xy = np.stack([pick % 4, pick // 4], axis=1) * base.h
         off[b, :n] = xy - xy.mean(axis=0)
@@ -162,10 +162,11 @@ def _ragged_pieces(rng, base, B):
                                      pack_cells=cells, pack_off=off, pack_solution=None, table=region)
 
 
-@pytest.mark.parametrize("B,N", [(16, 1000), (1, 77), (3, 1021)])
+@pytest.mark.parametrize("B,N", [(16, 1000), (1, 77), (3, 1021), (2, 500), (8, 300), (15, 257)])
 def test_pack_ragged_pieces(sp, orc, B, N):
     """Any pieces of 1..8 cells, up to the 16-piece maximum (128 lanes per particle), on
-    particle counts that leave a workgroup partly filled."""
+    particle counts that leave a workgroup partly filled; even piece counts exercise the
+    pairs at offset B/2, which only the smaller-numbered piece of each pair takes."""
     rng = np.random.default_rng(300 + B)
     base, pr, _ = synth.config("tetris5", 0)
     prob = _ragged_pieces(rng, base, B)
@@ -192,3 +193,25 @@ def test_pack_sample_yaw_steps(sp, orc, steps):
     j64 = np.round((x64[..., 2] + math.pi) / (2 * math.pi / steps)).astype(int)
     assert np.array_equal(j32, j64) and j64.min() == 0 and j64.max() == steps - 1
     assert np.abs(x32 - x64).max() <= 2e-6
+
+
+@pytest.mark.parametrize("B", [5, 12])
+def test_pack_small_pieces(sp, orc, B):
+    """Pieces of at most two cells: four lanes per piece, some of them past every piece's
+    last cell."""
+    rng = np.random.default_rng(700 + B)
+    base, pr, _ = synth.config("tetris5", 0)
+    prob = _ragged_pieces(rng, base, B, max_cells=2)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    x = f32(synth.random_placements(rng, prob, 400))
+    for phase in (0, 1):
+        c32, v32, g32 = (N_(t) for t in dev.place_cost(T(x), phase))
+        c64, v64, g64, kink = o.place_cost(x, phase)
+        check_cost(f"pack small B{B} ph{phase}", c32, c64, v32, v64)
+        keep = np.broadcast_to((kink >= KINK)[:, None], g64.shape[:2])
+        check_grad(f"pack small B{B} ph{phase}", g32, g64, keep)
+    xs = T(x)
+    K = pr.k_lin1 + pr.k_quad1
+    cq, vq = dev.place_optimize(xs, 1, K + 1)
+    c64, v64, _, _ = o.place_cost(N_(xs), 1, grad=False)
+    check_cost(f"pack small B{B} after descent", N_(cq), c64, N_(vq), v64)
