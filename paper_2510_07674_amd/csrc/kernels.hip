@@ -1964,42 +1964,49 @@ __device__ __forceinline__ void segment_ends(const KProb &P, const float *qg, co
     }
 }
 
-// Intermediate waypoint of each segment: eight lanes per (particle, segment), lane c <
-// mid_candidates draws the ends' midpoint + noise (counter (p, 2s + chunk, c, 3)) and
-// scores the seed path by arm-obstacle penetration at the draw and at the two points
-// halfway to the ends; the lowest score (first on ties) is written to waypoint (W-1)/2.
+// Intermediate waypoint of each segment: 32 lanes per (particle, segment), four per
+// candidate c < 8.  Candidate c < mid_candidates draws the ends' midpoint + noise
+// (counter (p, 2s + chunk, c, 3)) and is scored by arm-obstacle penetration at the draw
+// and at the two points halfway to the ends, one point per lane (the fourth lane adds
+// zero, so the sum is (draw + first half point) + second half point in every case); the
+// lowest score (first candidate on ties) is written to waypoint (W-1)/2.
 __global__ __launch_bounds__(256) void k_seed_mid(KProb P, int nP, int W, const float *qg, const float *qp,
                                                   const float *pose, uint64_t seed, float *q)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int grp = gid >> 3, c = gid & 7, NS = n_segments(P), C = P.mid_candidates;
-    if (grp >= nP * NS) return;  // whole 8-lane groups only
+    const int grp = gid >> 5, c = (gid >> 2) & 7, pt = gid & 3, NS = n_segments(P), C = P.mid_candidates;
+    if (grp >= nP * NS) return;  // whole 32-lane groups only
     const int p = grp / NS, s = grp % NS;
-    float qa[NJ], qb[NJ], qc[NJ], h1[NJ], h2[NJ], u[8];
+    float qa[NJ], qb[NJ], qc[NJ], qe[NJ], u[8];
     segment_ends(P, qg, qp, p, s, qa, qb);
     uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s), (uint64_t)c, 3u, u);
     uniforms4(seed, (uint64_t)p, (uint64_t)(2 * s + 1), (uint64_t)c, 3u, u + 4);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         qc[j] = fminf(fmaxf(0.5f * (qa[j] + qb[j]) + P.mid_noise * (2.f * u[j] - 1.f), P.lo[j]), P.hi[j]);
-        h1[j] = 0.5f * (qa[j] + qc[j]);
-        h2[j] = 0.5f * (qc[j] + qb[j]);
+        qe[j] = pt == 0 ? qc[j] : pt == 1 ? 0.5f * (qa[j] + qc[j]) : 0.5f * (qc[j] + qb[j]);
     }
-    float sc = INFINITY;
-    if (c < C) {
+    float part = 0.f;
+    if (c >= C) {
+        part = INFINITY;
+    } else if (C > 1 && pt < 3) {
         const float *pp = pose ? pose + (size_t)p * P.B * 4 : nullptr;  // p2p: no blocks, unused
         const int kind = 2 + (s & 1);  // transit or transfer interior
-        sc = C > 1 ? arm_clutter(P, qc, pp, s >> 1, kind) + arm_clutter(P, h1, pp, s >> 1, kind) +
-                         arm_clutter(P, h2, pp, s >> 1, kind)
-                   : 0.f;
+        part = arm_clutter(P, qe, pp, s >> 1, kind);
     }
-    const int lane = threadIdx.x & 63, g0 = lane & ~7;
-    const float best = group8_reduce(sc, OpMin());
-    const int src = g0 + __builtin_ctzll((__ballot(c < C && sc == best) >> g0) & 0xFFull);
+    const float sc = part + __shfl_xor(part, 1, 64);
+    const float tot = sc + __shfl_xor(sc, 2, 64);
+    float best = tot;
+    best = fminf(best, __shfl_xor(best, 4, 64));
+    best = fminf(best, __shfl_xor(best, 8, 64));
+    best = fminf(best, __shfl_xor(best, 16, 64));
+    const int lane = threadIdx.x & 63, g0 = lane & ~31;
+    const unsigned long long hit = __ballot(pt == 0 && c < C && tot == best);
+    const int src = g0 + __builtin_ctzll((hit >> g0) & 0xFFFFFFFFull);
     float qm[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qm[j] = __shfl(qc[j], src, 64);
-    if (c == 0) {
+    if (c == 0 && pt == 0) {
         float *o = q + (((size_t)p * NS + s) * W + (W - 1) / 2) * NJ;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) o[j] = qm[j];
@@ -2295,7 +2302,7 @@ hipError_t launch_ik_lift(const KProb &P, int nP, const float *pose, uint64_t se
 hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, const float *qp, const float *pose,
                             uint64_t seed, float *q, hipStream_t st)
 {
-    const long g = (long)nP * 2 * P.B * 8;
+    const long g = (long)nP * 2 * P.B * 32;  // 32 lanes per (particle, segment); p2p groups past NS exit
     hipLaunchKernelGGL(k_seed_mid, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, P, nP, W, qg, qp, pose, seed,
                        q);
     const int n = nP * 2 * P.B * W;
