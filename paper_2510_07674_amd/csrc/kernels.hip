@@ -263,14 +263,12 @@ __device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (
     return b;
 }
 
-// Narrow-phase passes (sphere chunks tested exactly against one box) of each wave in a
-// stage-2 iteration, double-buffered by iteration parity (s_wave_par: the buffer each
-// wave fills now).  A particle's waves meet at barriers every iteration, so its busiest
-// wave sets its pace, and the launch ends with the slowest particle; all waves of a
-// particle take an issue priority from that wave's count of the previous iteration
-// (see traj_particle).
-__shared__ int s_wave_work[2][16];
-__shared__ int s_wave_par[16];
+// Narrow-phase passes (sphere chunks tested exactly against one box) of each wave in the
+// current stage-2 iteration.  A particle's waves meet at barriers every iteration, so the
+// wave with the most contacts sets its particle's pace, and the launch ends with the
+// slowest particle; that wave takes a higher issue priority on its SIMD for the next
+// iteration (see traj_particle).
+__shared__ int s_wave_work[16];
 constexpr int PRIO_STEP = 48;  // narrow-phase passes per priority level (levels 0..3)
 
 template <bool GRAD, int CH>
@@ -325,10 +323,7 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
             }
         }
     }
-    if (nar && lane == 0) {
-        const int w = threadIdx.x >> 6;
-        s_wave_work[s_wave_par[w]][w] += nar;
-    }
+    if (nar && lane == 0) s_wave_work[threadIdx.x >> 6] += nar;
 }
 
 // Blocks as they stand while the lane's segment runs: b' < b at the placement variable
@@ -1217,28 +1212,16 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     }
     __syncthreads();
 
-    if (lane == 0) {
-        s_wave_work[0][wave] = 0;
-        s_wave_work[1][wave] = 0;
-        s_wave_par[wave] = 0;
-    }
+    if (lane == 0) s_wave_work[wave] = 0;
     if (MODE == 2) {
         const float b1 = P.beta1, b2 = P.beta2, eps = P.adam_eps;
         for (int k = a.k_begin; k < a.k_end; ++k) {
             {
-                // issue priority from the previous iteration's contact work of the
-                // particle's busiest wave: the particles that hold the launch back run
-                // first on their SIMDs (scheduling only; the arithmetic is the same).
-                // The previous iteration's buffer was complete before its barriers; this
-                // wave's entry of the other buffer was last read before them as well.
-                const int par = (k - a.k_begin) & 1;
-                int mx = 0;
-                for (int wv = 0; wv < nwave; ++wv) mx = max(mx, s_wave_work[par ^ 1][wv]);
-                const int lvl = __builtin_amdgcn_readfirstlane(mx) / PRIO_STEP;
-                if (lane == 0) {
-                    s_wave_work[par][wave] = 0;
-                    s_wave_par[wave] = par;
-                }
+                // issue priority from the previous iteration's contact work: the waves
+                // that hold their particles back run first on their SIMDs (scheduling
+                // only; the arithmetic is the same)
+                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / PRIO_STEP;
+                if (lane == 0) s_wave_work[wave] = 0;
                 if (lvl >= 3)
                     __builtin_amdgcn_s_setprio(3);
                 else if (lvl == 2)
