@@ -921,6 +921,28 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
         a.lam = F(L.lam);
         a.lam_stride = 15 * K.B;
     }
+    {
+        // When the particles do not all fit on the chip at once (4 waves of 128 VGPRs per
+        // SIMD), workgroups start as others finish and a costly particle started late sets
+        // the end of the launch: start them costliest first (longest processing time
+        // first), ranked by one cost evaluation of the seeded particles.  Every particle
+        // computes the same thing on whichever workgroup runs it.
+        int cus = 0;
+        SPASM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, prob->device));
+        const long waves = (long)cfg->M * (traj_threads(K.B, cfg->W) / 64);
+        if (waves > 16L * cus && cfg->M <= MAX_SORT) {
+            TrajArgs e{};
+            e.P = cfg->M;
+            e.W = cfg->W;
+            e.phase = 0;
+            e.q_in = F(L.q);
+            e.pose_in = F(L.pose);
+            e.cost = F(L.c2);
+            SPASM_HIP(launch_traj(K, 0, e, st));
+            SPASM_HIP(launch_sort_keys(0, cfg->M, F(L.c2), nullptr, 0.f, cfg->M, I(L.ord2), nullptr, nullptr, st));
+            a.perm = I(L.ord2);
+        }
+    }
     SPASM_HIP(hipEventRecord(ev[3], st));
     SPASM_HIP(launch_traj(K, 2, a, st));
     SPASM_HIP(hipEventRecord(ev[4], st));

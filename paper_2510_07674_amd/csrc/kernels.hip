@@ -1366,7 +1366,7 @@ template <int MODE, int CH>
 __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
 {
     extern __shared__ float s_mv[];
-    traj_particle<MODE, CH>(P, a, blockIdx.x, s_mv);
+    traj_particle<MODE, CH>(P, a, a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x, s_mv);
 }
 
 // Serving: one launch advances every active solve of one (thread count, sphere chunk)

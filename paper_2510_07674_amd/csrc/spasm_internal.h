@@ -77,6 +77,10 @@ struct TrajArgs {
     float *lam;
     int lam_stride;
     int opt_stride;     // floats per particle in opt (0: the two moment blocks only)
+    // nullable: particle order of the workgroups, particle perm[P - 1 - w] on workgroup w
+    // (the solve passes its particles sorted by ascending initial cost, so the launch
+    // starts with the costliest)
+    const int32_t *perm;
 };
 // mode 0: cost only, 1: cost + gradient (scaled by gout if given), 2: optimise
 hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st);

@@ -561,6 +561,14 @@ def test_solve_ttfs(sp):
     rt, tq, tp = dev.solve_ttfs(cfg, check_every=cfg.K, max_attempts=1)
     assert rt["attempts"] == 1 and rt["iters"] == cfg.K
     assert torch.equal(bq, tq) and torch.equal(bp, tp) and rt["viol"] == res["viol"]
+    # the 10-block tower does not fit the chip at once, so the plain solve starts its
+    # particles costliest first; the chunked path keeps the natural order, and every
+    # particle must still end bit for bit the same
+    prob, pr, cfg = synth.config("tower10", synth.certified_seeds("tower10")[0])
+    dev = sp.Problem(prob, pr)
+    res, bq, bp = dev.solve(cfg)
+    rt, tq, tp = dev.solve_ttfs(cfg, check_every=cfg.K, max_attempts=1)
+    assert torch.equal(bq, tq) and torch.equal(bp, tp) and rt["viol"] == res["viol"]
     for s in synth.certified_seeds("tiny")[:6]:
         prob, pr, cfg = synth.config("tiny", s)
         rt, tq, _ = sp.Problem(prob, pr).solve_ttfs(cfg, check_every=10, max_attempts=3)
