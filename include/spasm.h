@@ -289,6 +289,9 @@ int spasm_traj_init(spasm_problem prob, int32_t P, int32_t W, const float *d_qgr
  * order satisfying first; resample up to `retries` more rounds while none satisfies
  * (decided on the device).  Fixed goals (N1 = 0): every particle starts at the goals.
  * Then lift, seed, K Adam steps, final quadratic-phase evaluation and the best particle.
+ * When the particles need more waves than the device holds at once, they are ranked by
+ * one cost evaluation of the seeded state and launched costliest first; each particle's
+ * result does not depend on that order.
  * d_work: device workspace of spasm_solve_workspace() bytes (256-byte aligned).
  * d_best_q [2B][W][7] and d_best_pose [B][4] receive the returned particle; *out the
  * summary.  Synchronises the stream once at the end. */

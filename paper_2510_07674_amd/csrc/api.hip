@@ -773,10 +773,38 @@ size_t stage2_opt_bytes(const KProb &K, const spasm_solve_config &cfg)
 }
 }  // namespace spasm
 
+// When a solve's particles need more waves than the chip holds at once (4 waves of 128
+// VGPRs per SIMD), workgroups start as others finish and a costly particle started late
+// sets the end of the launch: rank the seeded particles by one cost-only evaluation (into
+// cost) so that the fused kernel takes them costliest first (longest processing time
+// first).  Every particle computes the same thing on whichever workgroup runs it.  Sets
+// a.perm to perm, or leaves it null when every particle is resident anyway.
+static int order_costliest_first(spasm_problem prob, const spasm_solve_config &cfg, const float *q, const float *pose,
+                                 float *cost, int32_t *perm, TrajArgs &a, hipStream_t st)
+{
+    const KProb &K = prob->kp;
+    int cus = 0;
+    SPASM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, prob->device));
+    const long waves = (long)cfg.M * (traj_threads(K.B, cfg.W) / 64);
+    if (waves <= 16L * cus || cfg.M > MAX_SORT) return SPASM_OK;
+    TrajArgs e{};
+    e.P = cfg.M;
+    e.W = cfg.W;
+    e.phase = 0;
+    e.q_in = q;
+    e.pose_in = pose;
+    e.cost = cost;
+    SPASM_HIP(launch_traj(K, 0, e, st));
+    SPASM_HIP(launch_sort_keys(0, cfg.M, cost, nullptr, 0.f, cfg.M, perm, nullptr, nullptr, st));
+    a.perm = perm;
+    return SPASM_OK;
+}
+
 extern "C" size_t spasm_solve_ttfs_workspace(spasm_problem prob, const spasm_solve_config *cfg)
 {
     if (check_cfg(prob, cfg)) return 0;
-    return align256(solve_layout(prob->kp, *cfg).total) + align256(stage2_opt_bytes(prob->kp, *cfg));
+    return align256(solve_layout(prob->kp, *cfg).total) + align256(stage2_opt_bytes(prob->kp, *cfg)) +
+           align256((size_t)cfg->M * sizeof(int32_t));
 }
 
 extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t check_every,
@@ -793,8 +821,8 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
     const KProb &K = prob->kp;
     const SolveLayout L = solve_layout(K, *cfg);
     const size_t opt_off = align256(L.total), obytes = stage2_opt_bytes(K, *cfg);
-    if (work_bytes < opt_off + align256(obytes))
-        return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, opt_off + align256(obytes));
+    const size_t perm_off = opt_off + align256(obytes), need = perm_off + align256((size_t)cfg->M * sizeof(int32_t));
+    if (work_bytes < need) return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, need);
     rc = ensure_attrs();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -840,6 +868,8 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
         a.k_lin2 = (int)std::lround(prob->lin_frac2 * ca.K);
         a.cost = F(L.c2);
         a.viol = F(L.v2);
+        rc = order_costliest_first(prob, ca, F(L.q), F(L.pose), F(L.c2), I(perm_off), a, st);
+        if (rc) return rc;
         for (int k0 = 1; k0 <= ca.K; k0 += check_every) {
             a.k_begin = k0;
             a.k_end = std::min(ca.K, k0 + check_every - 1) + 1;
@@ -921,28 +951,8 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
         a.lam = F(L.lam);
         a.lam_stride = 15 * K.B;
     }
-    {
-        // When the particles do not all fit on the chip at once (4 waves of 128 VGPRs per
-        // SIMD), workgroups start as others finish and a costly particle started late sets
-        // the end of the launch: start them costliest first (longest processing time
-        // first), ranked by one cost evaluation of the seeded particles.  Every particle
-        // computes the same thing on whichever workgroup runs it.
-        int cus = 0;
-        SPASM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, prob->device));
-        const long waves = (long)cfg->M * (traj_threads(K.B, cfg->W) / 64);
-        if (waves > 16L * cus && cfg->M <= MAX_SORT) {
-            TrajArgs e{};
-            e.P = cfg->M;
-            e.W = cfg->W;
-            e.phase = 0;
-            e.q_in = F(L.q);
-            e.pose_in = F(L.pose);
-            e.cost = F(L.c2);
-            SPASM_HIP(launch_traj(K, 0, e, st));
-            SPASM_HIP(launch_sort_keys(0, cfg->M, F(L.c2), nullptr, 0.f, cfg->M, I(L.ord2), nullptr, nullptr, st));
-            a.perm = I(L.ord2);
-        }
-    }
+    rc = order_costliest_first(prob, *cfg, F(L.q), F(L.pose), F(L.c2), I(L.ord2), a, st);
+    if (rc) return rc;
     SPASM_HIP(hipEventRecord(ev[3], st));
     SPASM_HIP(launch_traj(K, 2, a, st));
     SPASM_HIP(hipEventRecord(ev[4], st));

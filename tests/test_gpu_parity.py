@@ -561,9 +561,9 @@ def test_solve_ttfs(sp):
     rt, tq, tp = dev.solve_ttfs(cfg, check_every=cfg.K, max_attempts=1)
     assert rt["attempts"] == 1 and rt["iters"] == cfg.K
     assert torch.equal(bq, tq) and torch.equal(bp, tp) and rt["viol"] == res["viol"]
-    # the 10-block tower does not fit the chip at once, so the plain solve starts its
-    # particles costliest first; the chunked path keeps the natural order, and every
-    # particle must still end bit for bit the same
+    # the 10-block tower does not fit the chip at once: both paths launch its particles
+    # costliest first, and one chunk of K must still equal the fused launch bit for bit
+    # (order independence itself: test_gpu_serve.test_reordered_plain_solve_equals_served)
     prob, pr, cfg = synth.config("tower10", synth.certified_seeds("tower10")[0])
     dev = sp.Problem(prob, pr)
     res, bq, bp = dev.solve(cfg)

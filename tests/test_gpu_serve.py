@@ -78,6 +78,21 @@ def test_result_same_alone_and_in_mix(sp):
         assert res["viol"] == mixed[i]["result"]["viol"] and res["n_sat"] == mixed[i]["result"]["n_sat"]
 
 
+def test_reordered_plain_solve_equals_served(sp):
+    """1024 particles of 5 waves do not all fit on the chip at once, so the plain solve
+    launches them costliest first, while the serving launch takes them in natural order;
+    every particle computes the same on any workgroup, so the results are identical."""
+    dev, cfg = _req(sp, 7, 5, 30, 32, 1024, 30)
+    srv = sp.Server(2 << 30, max_slots=4, iters_per_step=10)
+    srv.submit(dev, cfg, 0)
+    out = _drain(srv)
+    srv.close()
+    res, bq, bp = dev.solve(cfg)
+    assert out[0]["status"] == 0
+    assert torch.equal(bq, out[0]["best_q"]) and torch.equal(bp, out[0]["best_pose"])
+    assert res["viol"] == out[0]["result"]["viol"] and res["n_sat"] == out[0]["result"]["n_sat"]
+
+
 def test_admission_follows_budget(sp):
     reqs = [_req(sp, 11, 2, 10, 16, 128, 40), _req(sp, 12, 2, 10, 16, 128, 40)]
     need = sp.Server.footprint(*reqs[0])
