@@ -236,6 +236,34 @@ int spasm_select_topm_large(int32_t N, const float *d_key, int32_t M, int32_t *d
 int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, int32_t *d_order,
                 int32_t *d_nsat, void *stream);
 
+/* --- sampled placements (Alg. 1 lines 1-4) ---------------------------------------------------
+ * Draws N placements (round `round` of the sample stream, as spasm_sample), scores each
+ * with the linear-phase placement cost (Alg. 1 Cost) and keeps the M lowest-cost samples
+ * (ArgSort[:M]: ascending cost, equal costs in sample order; N up to 2^20 as in
+ * spasm_select_topm_large).  d_place [M][B][3] the kept samples in that order, d_cost /
+ * d_viol [M] (nullable) their linear-phase cost and violation.  d_work:
+ * spasm_sample_placements_workspace(prob, N, M) bytes, 256-byte aligned (0 returned for an
+ * unsupported shape). */
+size_t spasm_sample_placements_workspace(spasm_problem prob, int32_t N, int32_t M);
+int spasm_sample_placements(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, int32_t round,
+                            void *d_work, size_t work_bytes, float *d_place, float *d_cost, float *d_viol,
+                            void *stream);
+
+/* --- whole stage 1 (Alg. 1 lines 1-23) -------------------------------------------------------
+ * The stage 1 that spasm_solve runs: rounds r = 0, 1, ... of sampling N placements, the
+ * linear score, the M best, the k_lin1 + k_quad1 descent and the satisfying-first order,
+ * until a round has a satisfying particle or 1 + retries rounds have run (the last round's
+ * particles are then kept anyway); the decision is taken on the device, later rounds'
+ * kernels exit at once.  Towers and packing problems; 1 <= M <= N <= 16384.
+ * d_pose [M][B][4]: the committed round's placements in satisfying-first order, as stage-2
+ * placement variables (x, y, slot-height z, yaw); d_cost / d_viol [M] (nullable): their
+ * quadratic-phase cost and violation; d_info [2] int32: satisfying particles of the
+ * committed round, rounds run.  d_work: spasm_stage1_workspace(prob, N, M) bytes, 256-byte
+ * aligned (0 returned for an unsupported problem or shape). */
+size_t spasm_stage1_workspace(spasm_problem prob, int32_t N, int32_t M);
+int spasm_stage1(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, void *d_work, size_t work_bytes,
+                 float *d_pose, float *d_cost, float *d_viol, int32_t *d_info, void *stream);
+
 /* --- placement only (Alg. 1, one round) ---------------------------------------------------
  * Stage 1 without trajectory optimisation: sample N placements (round `round` of the
  * sample stream), score them (linear phase), keep the M best (N up to 2^20 as in
@@ -299,17 +327,30 @@ size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_config *cfg);
 int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, void *d_work, size_t work_bytes,
                 float *d_best_q, float *d_best_pose, spasm_result *out, void *stream);
 
-/* Time to first solution (the paper's solve-time measure): attempts of the whole method.
- * Within an attempt the stage-2 descent runs in chunks of check_every iterations (Adam
- * moments kept in the workspace between chunks, so the iterates equal those of one
- * launch) and stops after the first chunk whose end state has a satisfying particle
- * (violation < sat_eps); an attempt that reaches K without one is followed by a new one
- * with fresh samples (seed + attempt * 0x9E3779B97F4A7C15), at most max_attempts.  The
- * returned particle is the best of the stopping chunk (satisfying first), or of the last
- * attempt.  out->total_ms is device time from the start to that chunk's result (HIP
- * events, including the host check between chunks); *attempts_out and *iters_out
- * (nullable) receive the attempts and stage-2 iterations run.  d_work:
- * spasm_solve_ttfs_workspace() bytes, 256-byte aligned. */
+/* Device memory one spasm_solve of this configuration occupies, in bytes: its workspace
+ * plus the d_best_q and d_best_pose outputs, each rounded up to 256 bytes (0 for an invalid
+ * configuration).  The stage-2 Adam moments live in on-chip memory during the fused
+ * launch and take no device memory; a served request also keeps them between steps (see
+ * spasm_server_footprint). */
+size_t spasm_solve_footprint(spasm_problem prob, const spasm_solve_config *cfg);
+
+/* Time to first solution (the paper's solve-time measure, Sec. IV: time until a first
+ * solution, at most 30,000 optimisation steps): attempts of the whole method.  Within an
+ * attempt the stage-2 descent runs in chunks of check_every iterations (Adam moments kept
+ * in the workspace between chunks, so the iterates equal those of one launch); after each
+ * chunk the device orders the particles and, at the first chunk whose end state has a
+ * satisfying particle (violation < sat_eps), sets a flag in the workspace that makes the
+ * later chunks of the attempt exit at entry.  All chunks of an attempt are enqueued at
+ * once and the host reads the outcome once per attempt.  An attempt that reaches K
+ * without a satisfying particle is followed by a new one with fresh samples (seed +
+ * attempt * 0x9E3779B97F4A7C15), at most max_attempts, and the stage-2 iterations of all
+ * attempts together stop at SPASM_TTFS_MAX_ITERS.  The returned particle is the best of
+ * the stopping chunk (satisfying first), or of the last attempt.  out->total_ms is device
+ * time from the start to the last attempt's result (HIP events); *attempts_out and
+ * *iters_out (nullable) receive the attempts and stage-2 iterations run (to the stopping
+ * chunk).  Requires K >= 1.  d_work: spasm_solve_ttfs_workspace() bytes, 256-byte
+ * aligned. */
+#define SPASM_TTFS_MAX_ITERS 30000
 size_t spasm_solve_ttfs_workspace(spasm_problem prob, const spasm_solve_config *cfg);
 int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t check_every,
                      int32_t max_attempts, void *d_work, size_t work_bytes, float *d_best_q,
@@ -322,13 +363,15 @@ int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t 
  * Each spasm_server_step:
  *   1. admits queued requests in arrival order while a slot is free and the request's
  *      footprint (spasm_server_footprint) fits in the arena, and runs their stage 1, lift
- *      and seeding on the admission stream; they join the launches from the next step;
- *   2. advances every ready solve by a chunk of stage-2 iterations in ONE launch per
- *      (thread count, sphere chunk) class -- solves of different block counts, waypoint
- *      counts and clutter share a launch, each particle is a workgroup, and the state stays
- *      on the device between steps.  Classes run on separate streams and overlap.  The
- *      slowest class (by measured time per iteration) advances iters_per_step iterations,
- *      the others as many as fit the same time (at most 64 iters_per_step);
+ *      and seeding on the admission stream, followed there by their first chunk of stage-2
+ *      iterations; they join the batched launches from the next step;
+ *   2. advances every other running solve by a chunk of stage-2 iterations in ONE launch
+ *      per (thread count, sphere chunk) class -- solves of different block counts,
+ *      waypoint counts and clutter share a launch, each particle is a workgroup, and the
+ *      state stays on the device between steps.  Classes run on separate streams and
+ *      overlap.  The slowest class (by measured time per iteration) advances
+ *      iters_per_step iterations or 2 ms of work, whichever is more, the others as many
+ *      as fit the same time (at most 64 iters_per_step);
  *   3. finishes solves that reached K (final evaluation, best particle written to the
  *      d_best_q [2B][W][7] / d_best_pose [B][4] buffers given at submit time) and queues
  *      their completion records;

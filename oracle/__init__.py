@@ -68,6 +68,9 @@ def lib():
         L.or_place_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp]
         L.or_traj_cost.argtypes = [P, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_traj_cost_al.argtypes = [P, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_traj_residuals.argtypes = [P, i, i, vp, vp, vp]
+        L.or_traj_slot_residuals.argtypes = [P, i, i, vp, vp, vp]
+        L.or_box_clearance.argtypes = [P, i, vp, vp, i, vp, vp]
         L.or_al_update.argtypes = [P, i, vp, d, vp]
         L.or_stage2_al.argtypes = [P, i, i, i, i, d, d, d, d, d, i, d, vp, vp, vp]
         L.or_schedule.argtypes = [i, i, d, d, vp, vp]
@@ -164,6 +167,32 @@ class Oracle:
         lib().or_traj_cost(self.ref, phase, P, W, _ptr(q), _ptr(pose), _ptr(cost), _ptr(viol),
                            _ptr(gq) if grad else None, _ptr(gp) if grad else None, _ptr(sk), _ptr(pk))
         return cost, viol, gq, gp, sk, pk
+
+    RESIDUALS = ("arm_box", "arm_block", "held_box", "held_block", "grasp", "tie", "limit", "place")
+
+    def traj_residuals(self, q, pose):
+        """Per particle, the largest residual of each kind in RESIDUALS (their maximum is the
+        violation): [P, 8]."""
+        q, pose = _f64(q), _f64(pose)
+        out = np.zeros((q.shape[0], len(self.RESIDUALS)))
+        lib().or_traj_residuals(self.ref, q.shape[0], q.shape[2], _ptr(q), _ptr(pose), _ptr(out))
+        return out
+
+    def traj_slot_residuals(self, q, pose):
+        """The breakdown per waypoint slot: [P, NS, W, 8] (placement entry zero)."""
+        q, pose = _f64(q), _f64(pose)
+        out = np.zeros(q.shape[:3] + (len(self.RESIDUALS),))
+        lib().or_traj_slot_residuals(self.ref, q.shape[0], q.shape[2], _ptr(q), _ptr(pose), _ptr(out))
+        return out
+
+    def box_clearance(self, q, pose, boxes):
+        """Smallest sdf - r of one plan (q [NS, W, 7], pose [B, 4]) against each box of
+        boxes [n, 6]: robot spheres at every slot, the held block inside transfers, every
+        block at its initial pose and at its placement."""
+        q, pose, boxes = _f64(q), _f64(pose), _f64(boxes).reshape(-1, 6)
+        out = np.zeros(boxes.shape[0])
+        lib().or_box_clearance(self.ref, q.shape[1], _ptr(q), _ptr(pose), boxes.shape[0], _ptr(boxes), _ptr(out))
+        return out
 
     def traj_cost_al(self, q, pose, lam, phase=LIN, grad=True):
         """Stage-2 cost with the multiplier terms lambda . e (lam [P, B, 15]); also returns
@@ -303,15 +332,19 @@ class Oracle:
         """Whole method in FP64: returns dict(success, viol, cost, q, pose, order info)."""
         prob, pr = self.prob, self.params
         if cfg.N1 > 0:
+            # Alg. 1: resample while no particle satisfies, at most `retries` more rounds;
+            # the last round's particles are lifted when none ever does
             for rnd in range(pr.retries + 1):
                 x, c1, v1 = self.stage1(cfg.N1, cfg.M, cfg.seed, rnd)
                 order, nsat = self.order(c1, v1)
                 if nsat > 0:
                     break
+            rounds = rnd + 1
             pose = self.initial_poses(x[order])
         else:
-            nsat = -1
+            nsat, rounds = -1, 0
             pose = np.repeat(_f64(prob.goal)[None], cfg.M, axis=0)
+        pose0 = pose
         qg, qp = self.ik_lift(pose, cfg.seed)
         q = self.traj_init(qg, qp, cfg.W, cfg.seed, pose)
         q, pose = self.stage2(q, pose, cfg.K)
@@ -319,4 +352,4 @@ class Oracle:
         order2, nsat2 = self.order(cost, viol)
         best = int(order2[0])
         return {"success": nsat2 > 0, "viol": viol, "cost": cost, "best": best, "n_sat": nsat2,
-                "stage1_sat": nsat, "q": q, "pose": pose}
+                "stage1_sat": nsat, "rounds": rounds, "pose0": pose0, "q": q, "pose": pose}

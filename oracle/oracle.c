@@ -20,6 +20,17 @@
  *                       + w_coll C_coll; C_trajopt = C_placement + w_start C_start
  *                       + w_arm C_arm + w_block C_block
  * Readings of points the paper leaves open are listed where they are used.
+ *
+ * Parity unpinned: the paper allows any parallel IK and any sampled intermediate
+ * waypoint, so two choices here are this implementation's own and nothing in the paper
+ * fixes them -- the multi-start lift's rule (among converged starts the one least deep in
+ * the clutter, ik_multistart) and the seeding's best-of-candidates rule for the
+ * intermediate waypoint (or_traj_init).  Tests check them only against restatements of
+ * the same rules; the GPU follows the same rules.
+ *
+ * Diagnostics (or_traj_residuals, or_traj_slot_residuals, or_box_clearance) take the
+ * violation apart by kind or measure a plan's clearance from boxes; they serve the scene
+ * builder and failure analysis, not parity.
  */
 #include "oracle.h"
 
@@ -577,9 +588,19 @@ void or_place_cost(const or_problem *pb, int dim, int phase, int N, const double
  *     position, x axis (yaw) and z axis                                 (C_tie)
  *   joint-limit hinges                                                  (C_lim)
  * ------------------------------------------------------------------------------------ */
+/* residual categories of the violation (or_traj_residuals) */
+enum { CAT_ARM_BOX, CAT_ARM_BLOCK, CAT_HELD_BOX, CAT_HELD_BLOCK, CAT_GRASP, CAT_TIE, CAT_LIMIT, CAT_PLACE, N_CAT };
+
 typedef struct {
     double cost, viol, kink, pose_kink;
+    double cat[N_CAT];
 } slot_out;
+
+static void note(slot_out *so, int cat, double r)
+{
+    so->viol = dmax(so->viol, r);
+    so->cat[cat] = dmax(so->cat[cat], r);
+}
 
 static void sphere_vs_targets(const or_problem *pb, int phase, double wgt, const frame F[9], int L,
                               const double *c, double r, int b, int tau, int w, int W,
@@ -594,7 +615,7 @@ static void sphere_vs_targets(const or_problem *pb, int phase, double wgt, const
         so->kink = dmin(so->kink, pair_kink(r, sdf, feat));
         if (delta > 0.0) {
             so->cost += wgt * phi(phase, delta);
-            so->viol = dmax(so->viol, delta);
+            note(so, arm ? CAT_ARM_BOX : CAT_HELD_BOX, delta);
             double s = -wgt * dphi(phase, delta), gc[3] = {s * g[0], s * g[1], s * g[2]};
             jac_point(F, L, c, gc, gq);
         }
@@ -622,7 +643,7 @@ static void sphere_vs_targets(const or_problem *pb, int phase, double wgt, const
         if (movable) so->pose_kink = dmin(so->pose_kink, km);
         if (delta > 0.0) {
             so->cost += wgt * phi(phase, delta);
-            so->viol = dmax(so->viol, delta);
+            note(so, arm ? CAT_ARM_BLOCK : CAT_HELD_BLOCK, delta);
             double s = -wgt * dphi(phase, delta), gc[3] = {s * gp[0], s * gp[1], s * gp[2]};
             jac_point(F, L, c, gc, gq);
             if (movable)
@@ -679,7 +700,7 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
         rz[2] = u[2] - 1.0;
         double c2 = dot3(rp, rp) + dot3(rz, rz);
         so->cost += w_start * c2;
-        so->viol = dmax(so->viol, sqrt(c2));
+        note(so, CAT_GRASP, sqrt(c2));
         double gp[3], gu[3];
         for (int i = 0; i < 3; ++i) {
             gp[i] = 2.0 * w_start * rp[i];
@@ -719,7 +740,7 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
         rz[2] = uz[2] - 1.0;
         double c2 = dot3(rp, rp) + dot3(rx, rx) + dot3(rz, rz);
         so->cost += w_tie * c2;
-        so->viol = dmax(so->viol, sqrt(c2));
+        note(so, CAT_TIE, sqrt(c2));
         double gp[3], gx[3], gz[3];
         for (int i = 0; i < 3; ++i) {
             gp[i] = 2.0 * w_tie * rp[i];
@@ -755,12 +776,12 @@ static void traj_slot(const or_problem *pb, int phase, int W, int s, int w, cons
         double eh = q[j] - pb->hi[j], el = pb->lo[j] - q[j];
         if (eh > 0.0) {
             so->cost += w_lim * phi(phase, eh);
-            so->viol = dmax(so->viol, eh);
+            note(so, CAT_LIMIT, eh);
             gq[j] += w_lim * dphi(phase, eh);
         }
         if (el > 0.0) {
             so->cost += w_lim * phi(phase, el);
-            so->viol = dmax(so->viol, el);
+            note(so, CAT_LIMIT, el);
             gq[j] -= w_lim * dphi(phase, el);
         }
     }
@@ -779,9 +800,100 @@ void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q
 /* The stage-2 cost with the augmented Lagrangian's multiplier terms: lam [P][B][15]
  * (nullable) adds lambda . e for each block's equality residual e (grasp alignment rp,
  * rz: components 0..5; tie rp, rx, rz: 6..14); e_out [P][B][15] (nullable) receives e. */
+static void traj_cost_impl(const or_problem *pb, int phase, int P, int W, const double *q, const double *pose,
+                           const double *lam, double *e_out, double *cost, double *viol, double *gq, double *gpose,
+                           double *slot_kink, double *pose_kink, double *cat_out, double *slot_cat_out);
+
 void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double *q, const double *pose,
                      const double *lam, double *e_out, double *cost, double *viol, double *gq, double *gpose,
                      double *slot_kink, double *pose_kink)
+{
+    traj_cost_impl(pb, phase, P, W, q, pose, lam, e_out, cost, viol, gq, gpose, slot_kink, pose_kink, NULL, NULL);
+}
+
+/* Diagnostics: per particle, the largest residual of each kind that makes up the
+ * violation -- arm spheres in a box, arm spheres in a block, held block in a box, held
+ * block in another block, grasp, tie, joint limit, placement cost of the pose variables
+ * (block-block / block-box penetration, stability, height) -- as cat [P][8]; their
+ * maximum is the violation. */
+void or_traj_residuals(const or_problem *pb, int P, int W, const double *q, const double *pose, double *cat)
+{
+    double *c = malloc(sizeof(double) * (size_t)P), *v = malloc(sizeof(double) * (size_t)P);
+    traj_cost_impl(pb, OR_QUAD, P, W, q, pose, NULL, NULL, c, v, NULL, NULL, NULL, NULL, cat, NULL);
+    free(v);
+    free(c);
+}
+
+/* The same breakdown per waypoint slot: slot_cat [P][NS][W][8] (the placement entry, a
+ * property of the pose variables, is left zero here). */
+void or_traj_slot_residuals(const or_problem *pb, int P, int W, const double *q, const double *pose,
+                            double *slot_cat)
+{
+    double *c = malloc(sizeof(double) * (size_t)P), *v = malloc(sizeof(double) * (size_t)P);
+    traj_cost_impl(pb, OR_QUAD, P, W, q, pose, NULL, NULL, c, v, NULL, NULL, NULL, NULL, NULL, slot_cat);
+    free(v);
+    free(c);
+}
+
+/* Clearance of a single-particle plan from candidate boxes (test infrastructure for
+ * building scenes around a known plan): for each box k of boxes [n][6] (centre, half
+ * extents), the smallest sdf_box(c) - r over every robot sphere at every waypoint slot,
+ * the held block's spheres at the interior waypoints of each transfer segment, and the
+ * block spheres of every block at its initial pose and at its placement pose[b]. */
+static double box_dist(const double *p, const double *box)
+{
+    double g[3];
+    return box_sdf_ex(p, box, g, NULL);
+}
+
+void or_box_clearance(const or_problem *pb, int W, const double *q, const double *pose, int n,
+                      const double *boxes, double *out)
+{
+    const int B = pb->B, NS = n_seg(pb);
+    const double h = pb->h, rb = 0.25 * h - pb->block_margin;
+    for (int k = 0; k < n; ++k) out[k] = INFINITY;
+    const double *G = pb->grasp;
+    frame Gi;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Gi.R[3 * i + j] = G[4 * j + i];
+    for (int i = 0; i < 3; ++i) Gi.p[i] = -(Gi.R[3 * i] * G[3] + Gi.R[3 * i + 1] * G[7] + Gi.R[3 * i + 2] * G[11]);
+    for (int s = 0; s < NS; ++s)
+        for (int w = 0; w < W; ++w) {
+            frame F[9], TB;
+            fk_frames(pb, q + ((size_t)s * W + w) * NJ, F);
+            for (int i = 0; i < pb->S; ++i) {
+                double c[3];
+                apply(&F[pb->sph_link[i]], pb->sph_c + 3 * i, c);
+                for (int k = 0; k < n; ++k) out[k] = dmin(out[k], box_dist(c, boxes + 6 * k) - pb->sph_r[i]);
+            }
+            if (s % 2 == 1 && w >= 1 && w <= W - 2) {
+                compose(&F[8], &Gi, &TB);
+                for (int m = 0; m < 8; ++m) {
+                    double sb[3], c[3];
+                    block_sphere(h, m, sb);
+                    apply(&TB, sb, c);
+                    for (int k = 0; k < n; ++k) out[k] = dmin(out[k], box_dist(c, boxes + 6 * k) - rb);
+                }
+            }
+        }
+    for (int b = 0; b < (pb->mode == 3 ? 0 : B); ++b)
+        for (int which = 0; which < 2; ++which) {
+            const double *P = which ? pose + 4 * b : pb->block_init + 4 * b;
+            const double cy = cos(P[3]), sy = sin(P[3]);
+            for (int m = 0; m < 8; ++m) {
+                double sb[3], c[3];
+                block_sphere(h, m, sb);
+                c[0] = P[0] + cy * sb[0] - sy * sb[1];
+                c[1] = P[1] + sy * sb[0] + cy * sb[1];
+                c[2] = P[2] + sb[2];
+                for (int k = 0; k < n; ++k) out[k] = dmin(out[k], box_dist(c, boxes + 6 * k) - rb);
+            }
+        }
+}
+
+static void traj_cost_impl(const or_problem *pb, int phase, int P, int W, const double *q, const double *pose,
+                           const double *lam, double *e_out, double *cost, double *viol, double *gq, double *gpose,
+                           double *slot_kink, double *pose_kink, double *cat_out, double *slot_cat_out)
 {
     const int B = pb->B, NS = n_seg(pb);
     const size_t qstride = (size_t)NS * W * NJ;
@@ -796,10 +908,10 @@ void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double
         for (int i = 0; i < 4 * B; ++i) gpo[i] = 0.0;
         if (gqp)
             for (size_t i = 0; i < qstride; ++i) gqp[i] = 0.0;
-        double c = 0.0, v = 0.0, pk = INFINITY;
+        double c = 0.0, v = 0.0, pk = INFINITY, cat[N_CAT] = {0.0};
         for (int s = 0; s < NS; ++s) {
             for (int w = 0; w < W; ++w) {
-                slot_out so = {0.0, 0.0, INFINITY, INFINITY};
+                slot_out so = {0.0, 0.0, INFINITY, INFINITY, {0.0}};
                 double *g = gqp ? gqp + ((size_t)s * W + w) * NJ : scratch;
                 if (!gqp)
                     for (int j = 0; j < NJ; ++j) scratch[j] = 0.0;
@@ -808,6 +920,10 @@ void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double
                           gpo, &so);
                 c += so.cost;
                 v = dmax(v, so.viol);
+                for (int k = 0; k < N_CAT; ++k) cat[k] = dmax(cat[k], so.cat[k]);
+                if (slot_cat_out)
+                    for (int k = 0; k < N_CAT; ++k)
+                        slot_cat_out[(((size_t)p * NS + s) * W + w) * N_CAT + k] = so.cat[k];
                 pk = dmin(pk, so.pose_kink);
                 if (slot_kink) slot_kink[((size_t)p * NS + s) * W + w] = so.kink;
             }
@@ -829,6 +945,9 @@ void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double
             place_one(pb, 4, phase, pp, &pc, &pv, gpl, &pkk);
         c += pc;
         v = dmax(v, pv);
+        cat[CAT_PLACE] = pv;
+        if (cat_out)
+            for (int k = 0; k < N_CAT; ++k) cat_out[(size_t)p * N_CAT + k] = cat[k];
         pk = dmin(pk, pkk);
         for (int i = 0; i < 4 * B; ++i) gpo[i] += gpl[i];
         cost[p] = c;
@@ -881,8 +1000,9 @@ static void adam1(double *x, double *m, double *v, double g, double lr, int t, d
 /* Stage-2 Adam step (Sec. III-B descends the whole trajectory; Adam with the torch
  * defaults).  Consecutive segments share their boundary configuration: the copies
  * q[s][W-1] and q[s+1][0] both receive the sum of their gradients, so with equal
- * moments they stay equal.  Pose variables are only optimised for towers (fixed goals
- * are given). */
+ * moments they stay equal.  The first configuration of the first segment is the robot's
+ * start (q_home, as seeded) and is not a variable; a single motion also keeps its goal.
+ * Pose variables are only optimised for towers (fixed goals are given). */
 void or_traj_adam_step(const or_problem *pb, int P, int W, double *q, double *pose, double *mq,
                        double *vq, double *mp, double *vp, const double *gq, const double *gpose,
                        double lr, int t, double b1, double b2, double eps)
@@ -892,7 +1012,8 @@ void or_traj_adam_step(const or_problem *pb, int P, int W, double *q, double *po
     for (int p = 0; p < P; ++p) {
         for (int s = 0; s < NS; ++s) {
             for (int w = 0; w < W; ++w) {
-                if (pb->mode == 3 && (w == 0 || w == W - 1)) continue; /* pinned start and goal */
+                if (s == 0 && w == 0) continue;                  /* the start stays at q_home */
+                if (pb->mode == 3 && w == W - 1) continue;       /* the goal of a single motion */
                 for (int j = 0; j < NJ; ++j) {
                     size_t i = p * qstride + ((size_t)s * W + w) * NJ + j;
                     double g = gq[i];

@@ -49,6 +49,11 @@ void or_place_cost(const or_problem *pb, int dim, int phase, int N, const double
 void or_traj_cost(const or_problem *pb, int phase, int P, int W, const double *q,
                   const double *pose, double *cost, double *viol, double *gq,
                   double *gpose, double *slot_kink, double *pose_kink);
+void or_traj_residuals(const or_problem *pb, int P, int W, const double *q, const double *pose, double *cat);
+void or_traj_slot_residuals(const or_problem *pb, int P, int W, const double *q, const double *pose,
+                            double *slot_cat);
+void or_box_clearance(const or_problem *pb, int W, const double *q, const double *pose, int n,
+                      const double *boxes, double *out);
 void or_traj_cost_al(const or_problem *pb, int phase, int P, int W, const double *q,
                      const double *pose, const double *lam, double *e_out, double *cost,
                      double *viol, double *gq, double *gpose, double *slot_kink,

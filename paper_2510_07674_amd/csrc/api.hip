@@ -263,6 +263,14 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         delete pb;
         return fail(SPASM_EHIP, "problem upload failed");
     }
+    for (auto &e : pb->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : pb->ev)
+                if (f) (void)hipEventDestroy(f);
+            (void)hipFree(pb->dmem);
+            delete pb;
+            return fail(SPASM_EHIP, "hipEventCreate failed");
+        }
     float *base = (float *)pb->dmem;
     KProb &K = pb->kp;
     std::memset(&K, 0, sizeof(K));
@@ -350,6 +358,8 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
 extern "C" void spasm_problem_destroy(spasm_problem prob)
 {
     if (!prob) return;
+    for (auto &e : prob->ev)
+        if (e) (void)hipEventDestroy(e);
     if (prob->dmem) (void)hipFree(prob->dmem);
     delete prob;
 }
@@ -594,6 +604,124 @@ extern "C" int spasm_place_round(spasm_problem prob, int32_t N, int32_t M, uint6
     return SPASM_OK;
 }
 
+namespace {
+struct SampleLayout {
+    size_t x1, c1, v1, idx, topm, total;
+};
+SampleLayout sample_layout(int B, int N, int M)
+{
+    SampleLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.x1 = take((size_t)N * B * 3 * sizeof(float));
+    L.c1 = take((size_t)N * sizeof(float));
+    L.v1 = take((size_t)N * sizeof(float));
+    L.idx = take((size_t)M * sizeof(int32_t));
+    L.topm = take(topm_workspace(N, M));
+    L.total = o;
+    return L;
+}
+
+struct Stage1Layout {
+    size_t x1, c1, v1, idx, xs, cs, vs, ord1, nsat1, done, total;
+};
+Stage1Layout stage1_layout(int B, int N, int M)
+{
+    Stage1Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.x1 = take((size_t)N * B * 3 * sizeof(float));
+    L.c1 = take((size_t)N * sizeof(float));
+    L.v1 = take((size_t)N * sizeof(float));
+    L.idx = take((size_t)M * sizeof(int32_t));
+    L.xs = take((size_t)M * B * 3 * sizeof(float));
+    L.cs = take((size_t)M * sizeof(float));
+    L.vs = take((size_t)M * sizeof(float));
+    L.ord1 = take((size_t)M * sizeof(int32_t));
+    L.nsat1 = take(sizeof(int32_t));
+    L.done = take(sizeof(int32_t));
+    L.total = o;
+    return L;
+}
+
+int check_stage1_shape(spasm_problem prob, int32_t N, int32_t M)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    if (prob->kp.mode != SPASM_MODE_TOWER && prob->kp.mode != SPASM_MODE_PACK)
+        return fail(SPASM_EUNSUPPORTED, "stage 1 places tower or packing blocks (fixed goals and point-to-point "
+                                        "problems have none to place)");
+    if (M < 1 || N < M || N > MAX_SORT)
+        return fail(SPASM_EUNSUPPORTED, "stage 1 needs 1 <= M <= N <= %d (N=%d, M=%d)", MAX_SORT, N, M);
+    return SPASM_OK;
+}
+}  // namespace
+
+extern "C" size_t spasm_sample_placements_workspace(spasm_problem prob, int32_t N, int32_t M)
+{
+    if (!prob || check_topm_shape(N, M)) return 0;
+    return sample_layout(prob->kp.B, N, M).total;
+}
+
+extern "C" int spasm_sample_placements(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, int32_t round,
+                                       void *d_work, size_t work_bytes, float *d_place, float *d_cost, float *d_viol,
+                                       void *stream)
+{
+    if (!prob) return fail(SPASM_EINVAL, "problem is NULL");
+    int rc = check_topm_shape(N, M);
+    if (rc) return rc;
+    if (round < 0) return fail(SPASM_EINVAL, "round=%d must be >= 0", round);
+    if (!d_place) return fail(SPASM_EINVAL, "NULL output buffer");
+    const SampleLayout L = sample_layout(prob->kp.B, N, M);
+    if (!d_work || work_bytes < L.total) return fail(SPASM_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, L.total);
+    if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace is not 256-byte aligned");
+    rc = ensure_attrs();
+    if (rc) return rc;
+    const KProb &K = prob->kp;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)d_work;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    SPASM_HIP(launch_sample(K, N, seed, round, F(L.x1), nullptr, st));
+    SPASM_HIP(launch_place(K, N, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1), nullptr, nullptr,
+                           st));
+    SPASM_HIP(launch_topm(N, F(L.c1), M, I(L.idx), w + L.topm, st));
+    SPASM_HIP(launch_gather_place(K.B, M, F(L.x1), F(L.c1), F(L.v1), I(L.idx), d_place, d_cost, d_viol, st));
+    return SPASM_OK;
+}
+
+extern "C" size_t spasm_stage1_workspace(spasm_problem prob, int32_t N, int32_t M)
+{
+    if (check_stage1_shape(prob, N, M)) return 0;
+    return stage1_layout(prob->kp.B, N, M).total;
+}
+
+extern "C" int spasm_stage1(spasm_problem prob, int32_t N, int32_t M, uint64_t seed, void *d_work, size_t work_bytes,
+                            float *d_pose, float *d_cost, float *d_viol, int32_t *d_info, void *stream)
+{
+    int rc = check_stage1_shape(prob, N, M);
+    if (rc) return rc;
+    if (!d_pose || !d_info) return fail(SPASM_EINVAL, "NULL output buffer");
+    const Stage1Layout L = stage1_layout(prob->kp.B, N, M);
+    if (!d_work || work_bytes < L.total) return fail(SPASM_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, L.total);
+    if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace is not 256-byte aligned");
+    rc = ensure_attrs();
+    if (rc) return rc;
+    char *w = (char *)d_work;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    const Stage1Bufs b{F(L.x1), F(L.c1), F(L.v1), I(L.idx), F(L.xs), F(L.cs), F(L.vs), I(L.ord1), I(L.nsat1),
+                       I(L.done), d_pose, d_cost, d_viol, d_info};
+    return enqueue_stage1(prob, N, M, seed, b, (hipStream_t)stream);
+}
+
 extern "C" int spasm_order(int32_t n, const float *d_cost, const float *d_viol, float eps, int32_t *d_order,
                            int32_t *d_nsat, void *stream)
 {
@@ -714,6 +842,29 @@ int check_cfg(spasm_problem prob, const spasm_solve_config *cfg)
     return check_traj_shape(prob->kp.B, cfg->M, cfg->W);
 }
 
+// Alg. 1 lines 1-23 on the device: rounds of sample -> linear score -> top-M -> descent ->
+// satisfying-first order, each round skipped (kernels exit at once) after a round has
+// committed; a round commits when it has a satisfying particle or is the last one.
+int enqueue_stage1(spasm_problem prob, int N1, int M, uint64_t seed, const Stage1Bufs &b, hipStream_t st)
+{
+    const KProb &K = prob->kp;
+    SPASM_HIP(launch_zero(b.done, 4, st));
+    SPASM_HIP(launch_zero(b.info, 8, st));
+    const int R = prob->retries;
+    for (int r = 0; r <= R; ++r) {
+        const int *skip = b.done;
+        SPASM_HIP(launch_sample(K, N1, seed, r, b.x1, skip, st));
+        SPASM_HIP(launch_place(K, N1, b.x1, nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, b.c1, b.v1, nullptr, skip, st));
+        SPASM_HIP(launch_sort_keys(0, N1, b.c1, nullptr, 0.f, M, b.idx, nullptr, skip, st));
+        SPASM_HIP(launch_place(K, M, b.x1, b.idx, b.xs, 1, prob->k_total1 + 1, SPASM_PHASE_QUAD, b.cs, b.vs, nullptr,
+                               skip, st));
+        SPASM_HIP(launch_sort_keys(1, M, b.cs, b.vs, prob->sat_eps, M, b.ord1, b.nsat1, skip, st));
+        SPASM_HIP(launch_commit_stage1(K, M, r, r == R, b.xs, b.cs, b.vs, b.ord1, b.nsat1, b.pose, b.cost_out,
+                                       b.viol_out, b.done, b.info, st));
+    }
+    return SPASM_OK;
+}
+
 int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L, hipStream_t st,
                    hipEvent_t after_stage1)
 {
@@ -722,21 +873,11 @@ int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, c
     auto I = [&](size_t o) { return (int32_t *)(w + o); };
     const int M = cfg.M, W = cfg.W;
     if (cfg.N1 > 0) {
-        SPASM_HIP(launch_zero(I(L.done), 4, st));
         SPASM_HIP(launch_zero(I(L.info), 32, st));
-        const int R = prob->retries;
-        for (int r = 0; r <= R; ++r) {
-            const int *skip = I(L.done);
-            SPASM_HIP(launch_sample(K, cfg.N1, cfg.seed, r, F(L.x1), skip, st));
-            SPASM_HIP(launch_place(K, cfg.N1, F(L.x1), nullptr, nullptr, 1, 1, SPASM_PHASE_LIN, F(L.c1), F(L.v1),
-                                   nullptr, skip, st));
-            SPASM_HIP(launch_sort_keys(0, cfg.N1, F(L.c1), nullptr, 0.f, M, I(L.idx), nullptr, skip, st));
-            SPASM_HIP(launch_place(K, M, F(L.x1), I(L.idx), F(L.xs), 1, prob->k_total1 + 1, SPASM_PHASE_QUAD,
-                                   F(L.cs), F(L.vs), nullptr, skip, st));
-            SPASM_HIP(launch_sort_keys(1, M, F(L.cs), F(L.vs), prob->sat_eps, M, I(L.ord1), I(L.nsat1), skip, st));
-            SPASM_HIP(launch_commit_stage1(K, M, r, r == R, F(L.xs), I(L.ord1), I(L.nsat1), F(L.pose), I(L.done),
-                                           I(L.info), st));
-        }
+        const Stage1Bufs b{F(L.x1), F(L.c1), F(L.v1), I(L.idx), F(L.xs), F(L.cs), F(L.vs), I(L.ord1), I(L.nsat1),
+                           I(L.done), F(L.pose), nullptr, nullptr, I(L.info)};
+        const int rc = enqueue_stage1(prob, cfg.N1, M, cfg.seed, b, st);
+        if (rc) return rc;
     } else {
         SPASM_HIP(launch_fixed_poses(K, M, F(L.pose), I(L.info), st));
     }
@@ -764,6 +905,15 @@ extern "C" size_t spasm_solve_workspace(spasm_problem prob, const spasm_solve_co
 {
     if (check_cfg(prob, cfg)) return 0;
     return solve_layout(prob->kp, *cfg).total;
+}
+
+extern "C" size_t spasm_solve_footprint(spasm_problem prob, const spasm_solve_config *cfg)
+{
+    if (check_cfg(prob, cfg)) return 0;
+    const KProb &K = prob->kp;
+    const size_t ns = K.mode == SPASM_MODE_P2P ? 1 : 2 * (size_t)K.B;
+    return align256(solve_layout(K, *cfg).total) + align256(ns * cfg->W * NJ * sizeof(float)) +
+           align256((size_t)K.B * 4 * sizeof(float));
 }
 
 namespace spasm {
@@ -804,7 +954,7 @@ extern "C" size_t spasm_solve_ttfs_workspace(spasm_problem prob, const spasm_sol
 {
     if (check_cfg(prob, cfg)) return 0;
     return align256(solve_layout(prob->kp, *cfg).total) + align256(stage2_opt_bytes(prob->kp, *cfg)) +
-           align256((size_t)cfg->M * sizeof(int32_t));
+           align256((size_t)cfg->M * sizeof(int32_t)) + 256;
 }
 
 extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t check_every,
@@ -816,12 +966,14 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
     if (rc) return rc;
     if (check_every < 1) return fail(SPASM_EINVAL, "check_every=%d must be >= 1", check_every);
     if (max_attempts < 1) return fail(SPASM_EINVAL, "max_attempts=%d must be >= 1", max_attempts);
+    if (cfg->K < 1) return fail(SPASM_EINVAL, "time to first solution needs K >= 1");
     if (!d_work || !d_best_q || !d_best_pose || !out) return fail(SPASM_EINVAL, "NULL buffer");
     if (((uintptr_t)d_work & 255) != 0) return fail(SPASM_EINVAL, "workspace must be 256-byte aligned");
     const KProb &K = prob->kp;
     const SolveLayout L = solve_layout(K, *cfg);
     const size_t opt_off = align256(L.total), obytes = stage2_opt_bytes(K, *cfg);
-    const size_t perm_off = opt_off + align256(obytes), need = perm_off + align256((size_t)cfg->M * sizeof(int32_t));
+    const size_t perm_off = opt_off + align256(obytes);
+    const size_t flag_off = perm_off + align256((size_t)cfg->M * sizeof(int32_t)), need = flag_off + 256;
     if (work_bytes < need) return fail(SPASM_EINVAL, "workspace %zu bytes < %zu needed", work_bytes, need);
     rc = ensure_attrs();
     if (rc) return rc;
@@ -829,33 +981,20 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
     char *w = (char *)d_work;
     auto F = [&](size_t o) { return (float *)(w + o); };
     auto I = [&](size_t o) { return (int32_t *)(w + o); };
-    hipEvent_t ev[2];
-    for (int i = 0; i < 2; ++i) SPASM_HIP(hipEventCreate(&ev[i]));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard()
-        {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } guard{ev};
-    int32_t *h_info = nullptr;
-    SPASM_HIP(hipHostMalloc((void **)&h_info, 8 * sizeof(int32_t) + 4 * sizeof(float)));
-    struct HostGuard {
-        int32_t *p;
-        ~HostGuard() { (void)hipHostFree(p); }
-    } hguard{h_info};
-    float *h_finfo = (float *)(h_info + 8);
+    int32_t *done = I(flag_off), *stop_iter = done + 1;
 
-    SPASM_HIP(hipEventRecord(ev[0], st));
+    SPASM_HIP(hipEventRecord(prob->ev[0], st));
     int att = 0, iters = 0;
+    int32_t info[8] = {0}, flags[2] = {0, 0};
+    float finfo[4] = {0.f};
     bool solved = false;
-    for (att = 0; att < max_attempts && !solved; ++att) {
+    for (att = 0; att < max_attempts && !solved && iters < SPASM_TTFS_MAX_ITERS; ++att) {
         spasm_solve_config ca = *cfg;
         ca.seed = cfg->seed + (uint64_t)att * 0x9E3779B97F4A7C15ull;  // fresh samples per attempt
         rc = enqueue_prefix(prob, ca, w, L, st);
         if (rc) return rc;
         SPASM_HIP(launch_zero(w + opt_off, obytes, st));
+        SPASM_HIP(launch_zero(done, 8, st));
         TrajArgs a{};
         a.P = ca.M;
         a.W = ca.W;
@@ -868,36 +1007,40 @@ extern "C" int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cf
         a.k_lin2 = (int)std::lround(prob->lin_frac2 * ca.K);
         a.cost = F(L.c2);
         a.viol = F(L.v2);
+        a.skip = done;
         rc = order_costliest_first(prob, ca, F(L.q), F(L.pose), F(L.c2), I(perm_off), a, st);
         if (rc) return rc;
-        for (int k0 = 1; k0 <= ca.K; k0 += check_every) {
+        // every chunk is enqueued at once; after the first chunk whose end state has a
+        // satisfying particle the device sets `done` and the later chunks exit at entry
+        const int k_last = std::min(ca.K, SPASM_TTFS_MAX_ITERS - iters);
+        for (int k0 = 1; k0 <= k_last; k0 += check_every) {
             a.k_begin = k0;
-            a.k_end = std::min(ca.K, k0 + check_every - 1) + 1;
+            a.k_end = std::min(k_last, k0 + check_every - 1) + 1;
             SPASM_HIP(launch_traj(K, 2, a, st));
-            iters += a.k_end - a.k_begin;
-            rc = enqueue_finish(prob, ca, w, L, d_best_q, d_best_pose, st);
-            if (rc) return rc;
-            SPASM_HIP(hipMemcpyAsync(h_info, I(L.info), 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            SPASM_HIP(hipMemcpyAsync(h_finfo, F(L.finfo), 4 * sizeof(float), hipMemcpyDeviceToHost, st));
-            SPASM_HIP(hipEventRecord(ev[1], st));
-            SPASM_HIP(hipStreamSynchronize(st));
-            if (h_info[2] > 0) {
-                solved = true;
-                break;
-            }
+            SPASM_HIP(launch_sort_keys(1, ca.M, F(L.c2), F(L.v2), prob->sat_eps, ca.M, I(L.ord2), I(L.nsat2), done, st));
+            SPASM_HIP(launch_check_stop(I(L.nsat2), done, stop_iter, a.k_end - 1, st));
         }
+        SPASM_HIP(launch_finalize(K, ca.M, ca.W, F(L.q), F(L.pose), F(L.c2), F(L.v2), I(L.ord2), I(L.nsat2),
+                                  d_best_q, d_best_pose, I(L.info), F(L.finfo), st));
+        SPASM_HIP(hipMemcpyAsync(info, I(L.info), sizeof(info), hipMemcpyDeviceToHost, st));
+        SPASM_HIP(hipMemcpyAsync(finfo, F(L.finfo), sizeof(finfo), hipMemcpyDeviceToHost, st));
+        SPASM_HIP(hipMemcpyAsync(flags, done, sizeof(flags), hipMemcpyDeviceToHost, st));
+        SPASM_HIP(hipEventRecord(prob->ev[1], st));
+        SPASM_HIP(hipStreamSynchronize(st));  // one host check per attempt
+        solved = flags[0] != 0;
+        iters += solved ? flags[1] : k_last;
     }
     float t = 0.f;
-    SPASM_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+    SPASM_HIP(hipEventElapsedTime(&t, prob->ev[0], prob->ev[1]));
     std::memset(out, 0, sizeof(*out));
-    out->stage1_sat = h_info[0];
-    out->rounds = h_info[1];
-    out->n_sat = h_info[2];
-    out->best = h_info[3];
-    out->success = h_info[2] > 0;
-    out->viol = h_finfo[0];
-    out->cost = h_finfo[1];
-    out->length = h_finfo[2];
+    out->stage1_sat = info[0];
+    out->rounds = info[1];
+    out->n_sat = info[2];
+    out->best = info[3];
+    out->success = info[2] > 0;
+    out->viol = finfo[0];
+    out->cost = finfo[1];
+    out->length = finfo[2];
     out->total_ms = t;
     if (attempts_out) *attempts_out = att;
     if (iters_out) *iters_out = iters;
@@ -921,15 +1064,7 @@ extern "C" int spasm_solve(spasm_problem prob, const spasm_solve_config *cfg, vo
     auto F = [&](size_t o) { return (float *)(w + o); };
     auto I = [&](size_t o) { return (int32_t *)(w + o); };
 
-    hipEvent_t ev[5];
-    for (int i = 0; i < 5; ++i) SPASM_HIP(hipEventCreate(&ev[i]));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard()
-        {
-            for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
-        }
-    } guard{ev};
+    hipEvent_t *ev = prob->ev;
 
     SPASM_HIP(hipEventRecord(ev[0], st));
     rc = enqueue_prefix(prob, *cfg, w, L, st, ev[1]);

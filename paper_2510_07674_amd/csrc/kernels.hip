@@ -1244,8 +1244,9 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
             __syncthreads();
             const float bc1 = 1.f - powf(b1, (float)k), bc2s = sqrtf(1.f - powf(b2, (float)k));
             const float step = lr / bc1, ibc2 = 1.f / bc2s;
-            // the start and goal of a point-to-point motion are pinned
-            if (sl.active && !(P.mode == SPASM_MODE_P2P && (sl.w == 0 || sl.w == W - 1))) {
+            // the start configuration (first waypoint of the first segment) is pinned
+            // at q_home in every mode, and so is the goal of a point-to-point motion
+            if (sl.active && !(sl.s == 0 && sl.w == 0) && !(P.mode == SPASM_MODE_P2P && sl.w == W - 1)) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
                     float gj = g[j];
@@ -1366,6 +1367,7 @@ template <int MODE, int CH>
 __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
 {
     extern __shared__ float s_mv[];
+    if (a.skip && __builtin_amdgcn_readfirstlane(*a.skip)) return;
     traj_particle<MODE, CH>(P, a, a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x, s_mv);
 }
 
@@ -1732,7 +1734,11 @@ __device__ __forceinline__ float ik_error(const KProb &P, int kind, float tx, fl
     return sqrtf(s);
 }
 
-__device__ __forceinline__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ], int iters)
+// Not inlined: the single-iteration entry point and the multi-start lift then run the
+// same instructions, so their iterates are bit-identical (inlined copies may contract
+// multiply-adds differently once `kind` is a constant).
+__device__ __noinline__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ],
+                                    int iters)
 {
     float sy, cy;
     sincosf(tyaw, &sy, &cy);
@@ -2051,8 +2057,9 @@ __global__ void k_traj_init(KProb P, int nP, int W, const float *qg, const float
 // particles (or is the last), its particles in satisfying-first order become the stage-2
 // placements (z at the slot height).  info: [0] stage-1 satisfying count, [1] rounds.
 __global__ __launch_bounds__(1024) void k_commit_stage1(KProb P, int M, int round, int last, const float *xs,
-                                                        const int32_t *order, const int32_t *nsat, float *pose,
-                                                        int *done, int32_t *info)
+                                                        const float *cs, const float *vs, const int32_t *order,
+                                                        const int32_t *nsat, float *pose, float *cost_out,
+                                                        float *viol_out, int *done, int32_t *info)
 {
     __shared__ int s_go;
     if (threadIdx.x == 0) s_go = (*done == 0) && (*nsat > 0 || last);
@@ -2067,6 +2074,10 @@ __global__ __launch_bounds__(1024) void k_commit_stage1(KProb P, int M, int roun
         o[1] = x[1];
         o[2] = zstar(P, b);
         o[3] = x[2];
+    }
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        if (cost_out) cost_out[m] = cs[order[m]];
+        if (viol_out) viol_out[m] = vs[order[m]];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -2311,11 +2322,26 @@ hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, cons
 }
 
 hipError_t launch_commit_stage1(const KProb &P, int M, int round, int last_round, const float *xs,
-                                const int32_t *order, const int32_t *nsat, float *pose, int *done, int32_t *info,
+                                const float *cs, const float *vs, const int32_t *order, const int32_t *nsat,
+                                float *pose, float *cost_out, float *viol_out, int *done, int32_t *info,
                                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_commit_stage1, dim3(1), dim3(1024), 0, st, P, M, round, last_round, xs, order, nsat, pose,
-                       done, info);
+    hipLaunchKernelGGL(k_commit_stage1, dim3(1), dim3(1024), 0, st, P, M, round, last_round, xs, cs, vs, order, nsat,
+                       pose, cost_out, viol_out, done, info);
+    return hipGetLastError();
+}
+
+__global__ void k_check_stop(const int32_t *nsat, int32_t *done, int32_t *stop_iter, int iters)
+{
+    if (threadIdx.x == 0 && *done == 0 && *nsat > 0) {
+        *done = 1;
+        *stop_iter = iters;
+    }
+}
+
+hipError_t launch_check_stop(const int32_t *nsat, int32_t *done, int32_t *stop_iter, int iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_stop, dim3(1), dim3(64), 0, st, nsat, done, stop_iter, iters);
     return hipGetLastError();
 }
 

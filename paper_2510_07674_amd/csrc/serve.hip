@@ -1,8 +1,8 @@
 // Continuous-batching solve server (host side): requests are admitted in arrival order
 // as slots and arena memory free up; an admitted request runs its prefix (stage 1, lift,
-// seeding) on the admission stream while the running solves advance, and from the next
-// step on it advances a chunk of stage-2 iterations per step inside one batched launch
-// per (thread count, sphere chunk) class.  Classes run on their own streams so that they
+// seeding) and its first chunk of stage-2 iterations on the admission stream while the
+// running solves advance, and from the next step on it advances a chunk per step inside
+// one batched launch per (thread count, sphere chunk) class.  Classes run on their own streams so that they
 // overlap on the device, and each class's chunk is sized from its measured time per
 // iteration so that a step takes about as long for every class: a small solve then
 // advances many iterations while a large one advances a few.  Finished solves are retired
@@ -31,6 +31,7 @@ struct Request {
 struct Slot {
     bool used = false;
     bool ready = false;  // prefix done: takes part in the class launches
+    bool fresh = false;  // admitted in this step: its first chunk follows its prefix on the admission stream
     Request r{};
     size_t off = 0, bytes = 0, opt_off = 0;
     SolveLayout L{};
@@ -40,6 +41,7 @@ struct Slot {
 
 constexpr int N_CLASS_STREAMS = 4;
 constexpr int MAX_CLASS_LAUNCHES = 64;  // timed class launches per step
+constexpr double MIN_STEP_MS = 2.0;     // a step advances every class by at least this much work
 
 using ClassKey = std::pair<int, int>;  // (threads, sphere chunk)
 
@@ -218,28 +220,42 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         int rc = enqueue_prefix(s.r.prob, s.r.cfg, srv->arena + s.off, s.L, sa);
         if (rc) return rc;
         SPASM_HIP(launch_zero(srv->arena + s.opt_off, opt_bytes(s.r.prob, s.r.cfg), sa));
+        s.ready = true;
+        s.fresh = true;
         admitted.push_back(si);
     }
     // 2. one batched launch per class of ready solves, each class on its own stream, with
     //    a chunk of iterations sized from the class's measured time per iteration
-    std::map<ClassKey, std::vector<int>> classes;
+    //    (solves admitted in this step form their own launches on the admission stream,
+    //    right behind their prefix, so a request that finds the server idle starts at once)
+    std::map<ClassKey, std::vector<int>> classes, fresh;
     for (size_t i = 0; i < srv->slots.size(); ++i) {
         const Slot &s = srv->slots[i];
-        if (s.used && s.ready) classes[{traj_threads(s.r.prob->kp.B, s.r.cfg.W), s.r.prob->kp.chunk}].push_back((int)i);
+        if (s.used && s.ready)
+            (s.fresh ? fresh : classes)[{traj_threads(s.r.prob->kp.B, s.r.cfg.W), s.r.prob->kp.chunk}].push_back((int)i);
     }
     double slowest = 0.0;
-    for (auto &cl : classes) {
-        auto it = srv->ms_per_iter.find(cl.first);
-        if (it != srv->ms_per_iter.end()) slowest = std::max(slowest, it->second);
-    }
-    const double step_ms = slowest * srv->iters;  // 0 until some class has been timed
+    for (auto *group : {&classes, &fresh})
+        for (auto &cl : *group) {
+            auto it = srv->ms_per_iter.find(cl.first);
+            if (it != srv->ms_per_iter.end()) slowest = std::max(slowest, it->second);
+        }
+    // 0 until some class has been timed; otherwise the slowest class's iters_per_step
+    // iterations, and at least MIN_STEP_MS of work
+    const double step_ms = slowest > 0.0 ? std::max(slowest * srv->iters, MIN_STEP_MS) : 0.0;
     struct Launch {
         ClassKey key;
         int stream, event, iters;
     };
     std::vector<Launch> launches;
     int nd = 0, li = 0;
-    for (auto &cl : classes) {
+    std::vector<std::pair<ClassKey, std::vector<int>>> order;
+    for (auto &cl : fresh) order.push_back(cl);
+    for (auto &cl : classes) order.push_back(cl);
+    const size_t n_fresh = fresh.size();
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        auto &cl = order[oi];
+        const bool is_fresh = oi < n_fresh;
         int chunk = srv->iters;
         auto it = srv->ms_per_iter.find(cl.first);
         if (step_ms > 0.0 && it != srv->ms_per_iter.end() && it->second > 0.0)
@@ -273,8 +289,8 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
             d.first = first;
             first += c.M;
         }
-        const int sidx = li % N_CLASS_STREAMS, eidx = li < MAX_CLASS_LAUNCHES ? li : -1;
-        hipStream_t cst = srv->cs[sidx];
+        const int sidx = is_fresh ? -1 : li % N_CLASS_STREAMS, eidx = li < MAX_CLASS_LAUNCHES ? li : -1;
+        hipStream_t cst = is_fresh ? sa : srv->cs[sidx];
         SPASM_HIP(hipMemcpyAsync(srv->d_desc + d0, srv->h_desc + d0, sizeof(ServeSolve) * (size_t)(nd - d0),
                                  hipMemcpyHostToDevice, cst));
         if (eidx >= 0) SPASM_HIP(hipEventRecord(srv->ev[2 * eidx], cst));
@@ -308,17 +324,13 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         else
             it->second = 0.5 * it->second + 0.5 * per;
     }
-    // 4. retire; requests admitted in this step are ready from the next one
+    // 4. retire
     int active = 0;
     for (size_t i = 0; i < srv->slots.size(); ++i) {
         Slot &s = srv->slots[i];
         if (!s.used) continue;
         s.steps++;
-        if (!s.ready) {
-            s.ready = true;
-            ++active;
-            continue;
-        }
+        s.fresh = false;
         s.k_done = s.k_next;
         if (!s.finishing) {
             ++active;
@@ -343,6 +355,7 @@ extern "C" int spasm_server_step(spasm_server srv, int32_t *n_active, int32_t *n
         srv->release(s.off, s.bytes);
         s.used = false;
         s.ready = false;
+        s.fresh = false;
         s.finishing = false;
     }
     if (n_active) *n_active = active;

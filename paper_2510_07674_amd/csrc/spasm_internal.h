@@ -81,6 +81,9 @@ struct TrajArgs {
     // (the solve passes its particles sorted by ascending initial cost, so the launch
     // starts with the costliest)
     const int32_t *perm;
+    // nullable device flag: when *skip != 0 the launch returns at once (time to first
+    // solution: chunks after the one that found a solution)
+    const int32_t *skip;
 };
 // mode 0: cost only, 1: cost + gradient (scaled by gout if given), 2: optimise
 hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t st);
@@ -120,9 +123,13 @@ hipError_t launch_traj_init(const KProb &P, int nP, int W, const float *qg, cons
                             uint64_t seed, float *q, hipStream_t st);
 
 // solve glue
+// Commits round `round` of stage 1 when no earlier round did and it has a satisfying
+// particle or is the last: pose[m] = placement xs[order[m]] at its slot height, cost_out /
+// viol_out (nullable) the matching cs / vs, *done = 1, info[0] = nsat, info[1] = rounds.
 hipError_t launch_commit_stage1(const KProb &P, int M, int round, int last_round, const float *xs,
-                                const int32_t *order, const int32_t *nsat, float *pose, int *done,
-                                int32_t *info, hipStream_t st);
+                                const float *cs, const float *vs, const int32_t *order, const int32_t *nsat,
+                                float *pose, float *cost_out, float *viol_out, int *done, int32_t *info,
+                                hipStream_t st);
 hipError_t launch_fixed_poses(const KProb &P, int M, float *pose, int32_t *info, hipStream_t st);
 hipError_t launch_finalize(const KProb &P, int M, int W, const float *q, const float *pose,
                            const float *cost, const float *viol, const int32_t *order,
@@ -141,6 +148,19 @@ struct SolveLayout {
 };
 SolveLayout solve_layout(const KProb &K, const spasm_solve_config &c);
 int check_cfg(spasm_problem prob, const spasm_solve_config *cfg);
+// Stage-1 buffers: samples, their scores, the kept indices, the descended placements and
+// their order (working), then the committed outputs (pose [M][B][4]; cost_out, viol_out
+// nullable) and the summary info[0..1]; done is the device flag that skips later rounds.
+struct Stage1Bufs {
+    float *x1, *c1, *v1;
+    int32_t *idx;
+    float *xs, *cs, *vs;
+    int32_t *ord1, *nsat1;
+    int32_t *done;
+    float *pose, *cost_out, *viol_out;
+    int32_t *info;
+};
+int enqueue_stage1(spasm_problem prob, int N1, int M, uint64_t seed, const Stage1Bufs &b, hipStream_t st);
 // Stage 1 (or fixed goals), lift and seeding into the workspace, on `st`.
 // after_stage1 (nullable) is recorded between stage 1 and the lift.
 int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L, hipStream_t st,
@@ -149,12 +169,16 @@ int enqueue_prefix(spasm_problem prob, const spasm_solve_config &cfg, char *w, c
 int enqueue_finish(spasm_problem prob, const spasm_solve_config &cfg, char *w, const SolveLayout &L,
                    float *best_q, float *best_pose, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+// Time to first solution: after a chunk's ordering, when *done == 0 and *nsat > 0, sets
+// *done = 1 and *stop_iter = iters (the stage-2 iterations run so far in the attempt).
+hipError_t launch_check_stop(const int32_t *nsat, int32_t *done, int32_t *stop_iter, int iters, hipStream_t st);
 
 }  // namespace spasm
 
 struct spasm_problem_s {
     spasm::KProb kp;
     void *dmem = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // the solves' timing events
     int device = 0;
     int k_total1 = 0;
     int retries = 0;

@@ -4,7 +4,7 @@ continuous-batching server, against the plain path that runs one solve per launc
 sequence in arrival order.  Arrival rates are fractions of the plain path's measured
 capacity on the same mix.  Latency = completion time - arrival time (wall clock).
 
-    python -m paper_2510_07674_amd.serve_bench --requests 60 --rates 0.3 0.6 0.9
+    python -m paper_2510_07674_amd.serve_bench --requests 1000 --rates 0.3 0.6 0.9
 """
 from __future__ import annotations
 
@@ -46,6 +46,8 @@ def run_plain(reqs, arr):
             work[key] = dev.make_workspace(cfg)
         dev.solve(cfg, work[key])
         lat.append(time.perf_counter() - t0 - ta)
+        if len(lat) % 250 == 0:
+            print(f"plain: {len(lat)} of {len(reqs)} done", flush=True)
     total = time.perf_counter() - t0
     return np.array(lat), total
 
@@ -67,6 +69,8 @@ def run_served(reqs, arr, budget, slots, iters):
         for c in srv.poll():
             lat[c["req_id"]] = time.perf_counter() - t0 - arr[c["req_id"]]
             results[c["req_id"]] = c
+            if len(lat) % 250 == 0:
+                print(f"served: {len(lat)} of {n} done", flush=True)
         if active == 0 and pending == 0 and nxt < n:
             wait = arr[nxt] - (time.perf_counter() - t0)
             if wait > 0:
@@ -76,14 +80,21 @@ def run_served(reqs, arr, budget, slots, iters):
     return np.array([lat[i] for i in range(n)]), total, results
 
 
-def summary(lat, total, n):
-    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "solves_per_s": n / total}
+def summary(lat, total, n, seed=0):
+    """p50 / p99 / mean latency in ms with 95 % bootstrap intervals (2000 resamples of the
+    requests), and throughput."""
+    ms = lat * 1e3
+    rng = np.random.default_rng(seed)
+    boot = ms[rng.integers(0, len(ms), size=(2000, len(ms)))]
+    ci = lambda v: [float(np.percentile(v, 2.5)), float(np.percentile(v, 97.5))]
+    return {"p50_ms": float(np.percentile(ms, 50)), "p50_ci95": ci(np.percentile(boot, 50, axis=1)),
+            "p99_ms": float(np.percentile(ms, 99)), "p99_ci95": ci(np.percentile(boot, 99, axis=1)),
+            "mean_ms": float(ms.mean()), "mean_ci95": ci(boot.mean(axis=1)), "solves_per_s": n / total}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.3, 0.6, 0.9])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=8.0)
@@ -105,7 +116,8 @@ def main():
         lp, tp = run_plain(reqs, arr)
         ls, ts, _ = run_served(reqs, arr, int(args.budget_gb * 2**30), args.slots, args.iters_per_step)
         out["rates"].append({"load": frac, "arrival_per_s": rate, "plain": summary(lp, tp, len(reqs)),
-                             "served": summary(ls, ts, len(reqs))})
+                             "served": summary(ls, ts, len(reqs)),
+                             "served_all_ok": all(r["status"] == 0 for r in _.values())})
         print(json.dumps(out["rates"][-1]), flush=True)
     print(json.dumps(out), flush=True)
 

@@ -72,10 +72,16 @@ SYMBOLS = {
     "spasm_place_workspace": ([c_vp, c_i32, c_i32], ctypes.c_size_t),
     "spasm_place_round": ([c_vp, c_i32, c_i32, c_u64, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp, c_vp],
                           c_i32),
+    "spasm_sample_placements_workspace": ([c_vp, c_i32, c_i32], ctypes.c_size_t),
+    "spasm_sample_placements": ([c_vp, c_i32, c_i32, c_u64, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp],
+                                c_i32),
+    "spasm_stage1_workspace": ([c_vp, c_i32, c_i32], ctypes.c_size_t),
+    "spasm_stage1": ([c_vp, c_i32, c_i32, c_u64, c_vp, ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
     "spasm_ik_iterate": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp], c_i32),
     "spasm_ik_lift": ([c_vp, c_i32, c_vp, c_u64, c_i32, c_vp, c_vp, c_vp], c_i32),
     "spasm_traj_init": ([c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_u64, c_vp, c_vp], c_i32),
     "spasm_solve_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
+    "spasm_solve_footprint": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
     "spasm_solve_ttfs_workspace": ([c_vp, ctypes.POINTER(SolveConfigDesc)], ctypes.c_size_t),
     "spasm_solve_ttfs": ([c_vp, ctypes.POINTER(SolveConfigDesc), c_i32, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp,
                           ctypes.POINTER(ResultDesc), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_vp], c_i32),
@@ -248,6 +254,31 @@ class Problem:
                                         _dev(x), _dev(cost), _dev(viol), _dev(nsat, dtype=torch.int32), _stream()))
         return x, cost, viol, nsat
 
+    def sample_placements(self, N, M, seed, rnd=0, work=None):
+        """Alg. 1 lines 1-4: the M lowest-cost of N samples (x [M, B, 3], cost [M], viol [M],
+        linear phase), on the device."""
+        need = load().spasm_sample_placements_workspace(self.handle, N, M)
+        if need == 0:
+            raise SpasmError(f"unsupported sample shape N={N} M={M}")
+        work = torch.empty(need, dtype=torch.uint8, device="cuda") if work is None else work
+        x, cost, viol = _empty(M, self.B, 3), _empty(M), _empty(M)
+        _check(load().spasm_sample_placements(self.handle, N, M, seed, rnd, _dev(work, dtype=torch.uint8),
+                                              work.numel(), _dev(x), _dev(cost), _dev(viol), _stream()))
+        return x, cost, viol
+
+    def stage1(self, N, M, seed, work=None):
+        """Alg. 1 lines 1-23 (the solve's stage 1): (pose [M, B, 4] satisfying first, cost [M],
+        viol [M] quadratic phase, info [2] int32 = satisfying count, rounds), on the device."""
+        need = load().spasm_stage1_workspace(self.handle, N, M)
+        if need == 0:
+            _check(-1)
+        work = torch.empty(need, dtype=torch.uint8, device="cuda") if work is None else work
+        pose, cost, viol = _empty(M, self.B, 4), _empty(M), _empty(M)
+        info = _empty(2, dtype=torch.int32)
+        _check(load().spasm_stage1(self.handle, N, M, seed, _dev(work, dtype=torch.uint8), work.numel(), _dev(pose),
+                                   _dev(cost), _dev(viol), _dev(info, dtype=torch.int32), _stream()))
+        return pose, cost, viol, info
+
     # ---- stage 2 ----------------------------------------------------------------------
     def traj_cost(self, q, pose, phase=PHASE_LIN, grad=True):
         P, NS, W, _ = q.shape
@@ -325,6 +356,14 @@ class Problem:
     def workspace_bytes(self, cfg) -> int:
         c = self.config_desc(cfg)
         n = load().spasm_solve_workspace(self.handle, ctypes.byref(c))
+        if n == 0:
+            raise SpasmError(load().spasm_last_error().decode())
+        return int(n)
+
+    def footprint(self, cfg) -> int:
+        """Device bytes of one plain solve: workspace plus outputs."""
+        c = self.config_desc(cfg)
+        n = load().spasm_solve_footprint(self.handle, ctypes.byref(c))
         if n == 0:
             raise SpasmError(load().spasm_last_error().decode())
         return int(n)

@@ -18,12 +18,14 @@ available; these synthetic towers-in-clutter stand in for them:
 * cube blocks of edge 0.05 m resting at random table poses, top-down grasp;
 * a 1 x 1 m table centred on the robot base (table top z = 0); blocks, goals and
   the tower live in a placement region in front of the robot, 0.2-0.55 m out;
-* axis-aligned box obstacles with sides ~ U[0.05, 0.3] m resting anywhere on the
-  table, kept out of a square around the base and small squares around the blocks'
-  initial poses and around a hidden tower site, so that a placement exists;
-* scene instances of a workload are the seeds listed by `certified_seeds` (every block's
-  grasp and every tower slot reachable, certified offline by the oracle's IK); this
-  module only reads that list.
+* axis-aligned box obstacles with sides ~ U[0.05, 0.3] m resting on the table;
+* the named solve workloads (tiny, tower4, tower10) are feasible by construction: their
+  boxes are the first O of a seeded sequence of candidate boxes (uniform over the table)
+  that clear, by at least 1 cm, a plan that solves the box-free scene exactly (built
+  offline by tests/golden/make_witness_scenes.py with the FP64 oracle); this module only
+  reads the list of accepted candidates (`witness_scenes`) and draws the candidates;
+* other scenes (the serving mix) keep their boxes out of a square around the base and
+  small squares around the blocks' initial poses and a hidden tower site.
 """
 from __future__ import annotations
 
@@ -72,6 +74,7 @@ class Problem:
     pack_solution: np.ndarray = None  # (B, 3) one exact packing (x, y, yaw), for tests
     sample_yaw_steps: int = 0       # stage-1 yaw samples: 0 uniform, n > 0 on n directions
     p2p_goal: np.ndarray = None     # (7,) goal configuration (MODE_P2P; the start is q_home)
+    site: np.ndarray = None         # (2,) the hidden tower site kept clear of clutter (MODE_TOWER)
 
     @property
     def S(self) -> int:
@@ -113,7 +116,10 @@ class Params:
     alpha2: float = 2e-4
     beta1: float = 0.9
     beta2: float = 0.999
-    adam_eps: float = 1e-8
+    # Adam's epsilon at the gradient a 1 mm grasp or tie residual produces (2 w r |J| ~ 0.1):
+    # smaller gradients take plain-descent steps instead of normalised ones, so the exactly
+    # lifted grasp and place configurations are not thrown off by the first steps
+    adam_eps: float = 0.1
     # lift / initialisation
     ik_iters: int = 50
     ik_restarts: int = 8      # multi-start lift: starts per (particle, block)
@@ -202,8 +208,9 @@ def _keep_out(cx, cy, hx, hy, pts, rad):
 
 
 def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
-                 h: float = 0.05) -> Problem:
-    """Draw one seeded problem.  Deterministic in (seed, B, O, S, mode, h)."""
+                 h: float = 0.05, boxes: np.ndarray = None) -> Problem:
+    """Draw one seeded problem.  Deterministic in (seed, B, O, S, mode, h).  With `boxes`
+    given ([n, 6]) those are the obstacles and O only seeds the draw."""
     rng = np.random.default_rng([seed, B, O, S, mode, 0x5A5A])
     dh, lo, hi = _chain(rng)
     sph_link, sph_c, sph_r = _spheres(rng, dh, S)
@@ -242,6 +249,10 @@ def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
         for i in range(B):
             goal[i] = [math.nan, math.nan, (i + 0.5) * h, math.nan]
 
+    site = np.array(g, dtype=np.float64) if mode != MODE_FIXED else None
+    if boxes is not None:
+        return _finish(dh, lo, hi, sph_link, sph_c, sph_r, np.asarray(boxes, dtype=np.float64).reshape(-1, 6), h,
+                       block_init, mode, goal, site)
     boxes = []
     tries = 0
     while len(boxes) < O and tries < 100000:
@@ -255,7 +266,10 @@ def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
             continue
         boxes.append([cx, cy, half[2], half[0], half[1], half[2]])
     boxes = np.array(boxes, dtype=np.float64).reshape(-1, 6)
+    return _finish(dh, lo, hi, sph_link, sph_c, sph_r, boxes, h, block_init, mode, goal, site)
 
+
+def _finish(dh, lo, hi, sph_link, sph_c, sph_r, boxes, h, block_init, mode, goal, site) -> Problem:
     # top-down grasp: end effector at the top-face centre, its z axis pointing down
     grasp = np.array([[1.0, 0.0, 0.0, 0.0],
                       [0.0, -1.0, 0.0, 0.0],
@@ -263,7 +277,18 @@ def make_problem(seed: int, B: int, O: int, S: int = 42, mode: int = MODE_TOWER,
     return Problem(dh=dh, lo=lo, hi=hi, tool_d=0.10, q_home=np.zeros(N_JOINTS),
                    sph_link=sph_link, sph_c=sph_c, sph_r=sph_r, boxes=boxes, h=h,
                    block_init=block_init, mode=mode, goal=goal, grasp=grasp,
-                   table=np.array(REGION, dtype=np.float64))
+                   table=np.array(REGION, dtype=np.float64), site=site)
+
+
+def candidate_boxes(seed: int, B: int, O: int, S: int, mode: int, n: int) -> np.ndarray:
+    """The first n of a scene's seeded sequence of candidate boxes: sides U[0.05, 0.3] m,
+    centre uniform over the table, resting on it.  [n, 6] centre, half extents."""
+    rng = np.random.default_rng([seed, B, O, S, mode, 0xB0C5])
+    u = rng.uniform(size=(n, 5))  # one row per candidate: the first k rows do not depend on n
+    half = (0.05 + 0.25 * u[:, :3]) / 2
+    cx = TABLE[0] + (TABLE[1] - TABLE[0]) * u[:, 3]
+    cy = TABLE[2] + (TABLE[3] - TABLE[2]) * u[:, 4]
+    return np.stack([cx, cy, half[:, 2], half[:, 0], half[:, 1], half[:, 2]], axis=1)
 
 
 def _partition(rng: np.random.Generator, rows: int, cols: int, B: int) -> np.ndarray:
@@ -358,14 +383,52 @@ def make_p2p(seed: int, O: int = 20, S: int = 42) -> Problem:
                                goal=np.array([[math.nan, math.nan, base.h / 2, math.nan]]))
 
 
-_SEEDS_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
-                           "reachable_seeds.txt")
+_GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
+_SEEDS_FILE = os.path.join(_GOLDEN, "reachable_seeds.txt")
+_WITNESS_FILE = os.path.join(_GOLDEN, "witness_scenes.txt")
+WITNESS_WORKLOADS = ("tiny", "tower4", "tower10")
+# (B, O, S, mode) of the scenes of each named solve workload
+SCENES = {"tiny": (1, 10, 42, MODE_FIXED), "tower4": (4, 40, 42, MODE_TOWER), "tower10": (10, 80, 48, MODE_TOWER)}
+
+
+def witness_scenes(name: str) -> dict:
+    """{seed: accepted candidate-box indices} of a workload's feasible-by-construction
+    scenes (list written by tests/golden/make_witness_scenes.py)."""
+    out = {}
+    with open(_WITNESS_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if parts and parts[0] == name:
+                out[int(parts[1])] = [int(v) for v in parts[2:]]
+    if not out:
+        raise KeyError(name)
+    return out
+
+
+def witness_problem(name: str, seed: int, boxes_idx=None) -> Problem:
+    """Scene `seed` of a named solve workload: the seeded chain, spheres and blocks with
+    the accepted candidate boxes (`boxes_idx`, default: the recorded ones; [] = no boxes).
+    A seed that is not listed gives a scene of the same sizes whose boxes are only kept out
+    of the squares around the base, blocks and tower site (not certified feasible; parity
+    tests use such scenes too)."""
+    B, O, S, mode = SCENES[name]
+    if boxes_idx is None:
+        listed = witness_scenes(name)
+        if seed not in listed:
+            return make_problem(seed, B=B, O=O, S=S, mode=mode)
+        boxes_idx = listed[seed]
+    idx = list(boxes_idx)
+    n = max(idx) + 1 if idx else 0
+    boxes = candidate_boxes(seed, B, O, S, mode, n)[idx] if idx else np.zeros((0, 6))
+    return make_problem(seed, B=B, O=O, S=S, mode=mode, boxes=boxes)
 
 
 def certified_seeds(name: str) -> list:
-    """Scene seeds of a workload whose every block grasp and tower slot were found
-    reachable (list written by tests/golden/make_reachable_seeds.py).  Random chains
-    sometimes cannot reach a top-down grasp at all; those scenes are not instances."""
+    """Scene seeds of a workload.  tiny, tower4, tower10: the scenes built around a plan
+    that solves them (witness_scenes), in seed order; p2p: the seeds whose start and goal
+    are collision-free (list written by tests/golden/make_reachable_seeds.py)."""
+    if name in WITNESS_WORKLOADS:
+        return sorted(witness_scenes(name))
     with open(_SEEDS_FILE) as f:
         for line in f:
             parts = line.split()
@@ -394,13 +457,13 @@ def p2p_seeds() -> list:
 def config(name: str, seed: int = 0):
     """Return (problem, params, solve_config) for a named workload."""
     if name == "tiny":           # 1 block to a fixed target, 10 boxes, 2 x 16 waypoints
-        prob = make_problem(seed, B=1, O=10, S=42, mode=MODE_FIXED)
+        prob = witness_problem(name, seed)
         return prob, Params(), SolveConfig(N1=0, M=64, W=16, K=50, seed=seed)
     if name == "tower4":         # 4-block tower, 40 boxes, 8 x 32 waypoints
-        prob = make_problem(seed, B=4, O=40, S=42)
+        prob = witness_problem(name, seed)
         return prob, Params(), SolveConfig(N1=4096, M=1024, W=32, K=200, seed=seed)
     if name == "tower10":        # 10-block tower, 80 boxes, 20 x 32 waypoints, 48 spheres
-        prob = make_problem(seed, B=10, O=80, S=48)
+        prob = witness_problem(name, seed)
         return prob, Params(), SolveConfig(N1=16384, M=2048, W=32, K=300, seed=seed)
     if name == "p2p":            # one motion between two configurations among 20 boxes
         prob = make_p2p(seed, O=20)

@@ -159,6 +159,21 @@ def test_topm_and_place_shapes():
     assert L.spasm_place_round(None, 100, 10, 0, 0, None, 0, dummy, None, None, dummy, None) == -1
 
 
+def test_stage1_and_footprint_need_a_problem():
+    """The sampled-placement, whole-stage-1 and footprint calls refuse a NULL problem on the
+    host (0 bytes from the sizing calls, SPASM_EINVAL from the others)."""
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    dummy = ctypes.c_void_p(256)
+    assert L.spasm_sample_placements_workspace(None, 100, 10) == 0
+    assert L.spasm_sample_placements(None, 100, 10, 0, 0, dummy, 1 << 20, dummy, None, None, None) == -1
+    assert L.spasm_stage1_workspace(None, 100, 10) == 0
+    rc = L.spasm_stage1(None, 100, 10, 0, dummy, 1 << 20, dummy, None, None, dummy, None)
+    assert rc == -1 and "NULL" in L.spasm_last_error().decode()
+    cfg = spasm.SolveConfigDesc(4096, 1024, 32, 200, 0)
+    assert L.spasm_solve_footprint(None, ctypes.byref(cfg)) == 0
+
+
 @pytest.mark.parametrize("mutate", [
     "pack_no_cells", "pack_zero_cells", "pack_nine_cells", "pack_nan_offset", "yaw_steps_high", "yaw_steps_neg",
     "p2p_two_blocks", "p2p_no_goal", "p2p_goal_outside", "p2p_start_outside", "al_every_neg", "al_rho_neg",

@@ -14,6 +14,7 @@ penalty switches on or changes face, and FP32 position noise may decide differen
 the excluded fraction is bounded.  Integer results (top-M, order) are compared bit for
 bit, with both sides sorting the same FP32 keys.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -346,16 +347,18 @@ def test_place_optimize_teacher_forced(sp, orc):
     assert torch.equal(xa, xb)
 
 
-@pytest.mark.parametrize("name,W,P", [("tiny", 16, 32), ("tower4", 32, 4), ("p2p", 32, 16)])
-def test_traj_optimize_teacher_forced(sp, orc, name, W, P):
+@pytest.mark.parametrize("name,W,P,K", [("tiny", 16, 32, None), ("tower4", 32, 4, None), ("p2p", 32, 16, None),
+                                         ("tower10", 32, 2, 12)])
+def test_traj_optimize_teacher_forced(sp, orc, name, W, P, K):
     """Each Adam step from the GPU state: the oracle recomputes the gradient in FP64 and
-    applies its own step to the same state and moments."""
+    applies its own step to the same state and moments.  The 10-block tower runs 12
+    iterations of a 12-iteration schedule (10 linear, 2 quadratic)."""
     rng = np.random.default_rng(900)
     prob, pr, cfg = synth.config(name, 7)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
     q0, pose0 = _states("lifted", prob, pr, orc, rng, P, W)
     q, pose = T(f32(q0)), T(f32(pose0))
-    K = cfg.K
+    K = cfg.K if K is None else K
     opt = dev.opt_state(P, W)
     nq = 2 * prob.B * W * 7          # moment layout per particle: q (2B segments) then pose
     per = nq + 4 * prob.B
@@ -430,7 +433,9 @@ def test_ik_iterate_teacher_forced(sp, orc):
         step = np.linalg.norm(ref - q, axis=1)
         err = np.linalg.norm(g - ref, axis=1)
         report(f"ik step kind{kind}", max_rel=float(np.max(err / (step + 1e-6))))
-        assert np.all(err <= 2e-3 * step + 1e-5)
+        # FP32 residual and Jacobian (relative error ~1e-7 each) through a system of
+        # condition number <= (|J|^2 + lambda^2) / lambda^2 ~ 400: ~1e-4 relative
+        assert np.all(err <= 1e-4 * step + 1e-6)
 
 
 def _block_residual(o, prob, q, tgt, kind):
@@ -445,38 +450,143 @@ def _block_residual(o, prob, q, tgt, kind):
     return e
 
 
+def _u24(seed, ctr):
+    """Four 24-bit uniforms of Philox4x64-10 at counter ctr with key (seed, 0), from numpy
+    (which advances its counter before a block: start one below, with borrow)."""
+    v = sum(int(c) << (64 * i) for i, c in enumerate(ctr)) - 1
+    prev = np.array([(v >> (64 * i)) & (2**64 - 1) for i in range(4)], np.uint64)
+    raw = np.random.Philox(key=np.array([seed, 0], np.uint64), counter=prev).random_raw(4)
+    return (raw >> np.uint64(40)).astype(np.float64) / 2.0**24
+
+
+def _lift_starts(prob, pr, seed, p, sub, first, fused=False):
+    """The lift's starts for one (particle, solve): start 0 given, start r >= 1 uniform over
+    the limits, lo + (hi - lo) u from counter (p, sub + chunk, r, 2), in FP32 -- rounded
+    after the product and again after the sum, or once (fused multiply-add, which the
+    device compiler may emit: the FP64 sum of the exact product is exact here)."""
+    lo, hi = prob.lo.astype(np.float32), prob.hi.astype(np.float32)
+    span = (hi - lo).astype(np.float32)
+    out = [np.asarray(first, np.float32)]
+    for r in range(1, pr.ik_restarts):
+        u = np.concatenate([_u24(seed, (p, sub, r, 2)), _u24(seed, (p, sub + 1, r, 2))])[:7].astype(np.float32)
+        if fused:
+            out.append((span.astype(np.float64) * u.astype(np.float64) + lo.astype(np.float64)).astype(np.float32))
+        else:
+            out.append((lo + span * u).astype(np.float32))
+    return np.stack(out)
+
+
+def _ik_runs(sp, dev, o, prob, pr, kind, targets, starts):
+    """Each start's 50 damped least-squares iterations on the device and in the oracle.
+    Returns the final FP32 and FP64 configurations and whether the FP64 map is well
+    conditioned at that start: six random 1e-6 rad perturbations of the start move the
+    oracle's result by less than 1e-5 rad.  FP32 rounds every iteration by ~1e-7 rad, so
+    only there can the two precisions be expected to reach the same point; elsewhere the
+    iteration amplifies small differences (the solutions of a 5- or 6-constraint target
+    form a manifold in the 7 joint angles along which the damped steps drift; a converged
+    start amplifies a 1e-6 perturbation by 46x at the median) and either result is a
+    valid local solution."""
+    n = starts.shape[0]
+    tq, tt = T(starts), T(targets)
+    dev.ik_iterate(kind, tt, tq, pr.ik_iters)
+    q32 = N(tq)
+    one = T(starts)
+    for _ in range(pr.ik_iters):
+        dev.ik_iterate(kind, tt, one, 1)
+    assert torch.equal(one, tq)  # one launch of 50 iterations = 50 launches of one
+    s64 = starts.astype(np.float64)
+    q64 = np.stack([o.ik_iterate(kind, targets[i], s64[i], pr.ik_iters) for i in range(n)])
+    rng = np.random.default_rng(77)
+    stable = np.ones(n, bool)
+    for _ in range(6):
+        sp_ = np.clip(s64 + rng.uniform(-1e-6, 1e-6, s64.shape), prob.lo, prob.hi)
+        qp = np.stack([o.ik_iterate(kind, targets[i], sp_[i], pr.ik_iters) for i in range(n)])
+        stable &= np.abs(qp - q64).max(axis=1) < 1e-5
+    return q32, q64, stable
+
+
+def _pick_candidates(o, kind, targets, sols, pose, b):
+    """The lift's rule on given per-start solutions, evaluated in FP64: among the starts
+    with error < 1e-4 the smallest clutter score (first on ties), else the smallest error.
+    Returns the starts that FP32 may pick: those within 1e-5 of the deciding minimum
+    (errors within 1e-6 of the 1e-4 acceptance threshold count both ways)."""
+    err = np.array([o.ik_error(kind, targets[r], sols[r]) for r in range(len(sols))])
+    acc = err < 1e-4
+    amb = np.abs(err - 1e-4) < 1e-6
+    if (acc | amb).any():
+        pen = np.array([o.arm_clutter(sols[r], pose, b, kind) if acc[r] or amb[r] else np.inf
+                        for r in range(len(sols))])
+        m = np.min(pen[acc]) if acc.any() else np.min(pen)
+        cand = np.nonzero((acc | amb) & (pen <= m + 1e-5))[0]
+        if not acc.any():
+            cand = np.union1d(cand, [int(np.argmin(err))])
+        return cand
+    return np.nonzero(err <= np.min(err) + 1e-6)[0]
+
+
 def test_ik_lift_parity(sp, orc):
-    """50-iteration lift.  The chain is redundant (7 joints, 5 or 6 constraints) and the
-    limit clamp is discontinuous, so FP32 and FP64 may converge to different valid
-    configurations; single iterations are compared in test_ik_iterate_teacher_forced.
-    Here: the FP32 solutions reach their targets (residual measured in FP64) at the same
-    rate as the FP64 solves, and agree with them where both converged to one basin."""
+    """The multi-start lift, start by start.  Every start's 50 damped least-squares
+    iterations on the device agree with the FP64 oracle's from the same FP32 start where
+    the start converged and the FP64 iteration is well conditioned (see _ik_runs); and the
+    device's chosen grasp and placement configurations obey the lift's rule over the
+    device's own per-start solutions (errors and clutter scores evaluated in FP64;
+    near-ties within FP32 resolution admit either)."""
     rng = np.random.default_rng(1001)
     prob, pr, _ = synth.config("tower4", 9)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
-    P = 64
+    P, B, R, seed = 24, prob.B, pr.ik_restarts, 5
     pose = f32(o.initial_poses(synth.clustered_placements(rng, prob, P, spread=0.01)))
-    qg32, qp32 = (N(t) for t in dev.ik_lift(T(pose), seed=5))
-    qg64, qp64 = o.ik_lift(pose, seed=5)
-
-    def residuals(qg, qp):
-        rg = np.array([[_block_residual(o, prob, qg[p, b], prob.block_init[b], 0) for b in range(prob.B)]
-                       for p in range(P)])
-        rp = np.array([[_block_residual(o, prob, qp[p, b], pose[p, b], 1) for b in range(prob.B)]
-                       for p in range(P)])
-        return rg, rp
-
-    rg64, rp64 = residuals(qg64, qp64)
-    rg32, rp32 = residuals(qg32, qp32)
-    cg64, cp64 = rg64 < 1e-5, rp64 < 1e-5
-    cg32, cp32 = rg32 < 1e-4, rp32 < 1e-4
-    same_g = np.abs(qg32 - qg64).max(-1) < 1e-3
-    report("ik lift", grasp_conv64=float(cg64.mean()), grasp_conv32=float(cg32.mean()),
-           place_conv64=float(cp64.mean()), place_conv32=float(cp32.mean()),
-           same_basin=float(same_g[cg64 & cg32].mean()))
-    assert cg64.mean() > 0.5
-    assert abs(cg32.mean() - cg64.mean()) <= 0.1 and abs(cp32.mean() - cp64.mean()) <= 0.1
-    assert same_g[cg64 & cg32].mean() > 0.7
+    qg32, qp32 = (N(t) for t in dev.ik_lift(T(pose), seed=seed))
+    worst, compared, picked = 0.0, 0, 0
+    for kind in (0, 1):
+        starts = np.zeros((P, B, R, 7), np.float32)
+        fused = np.zeros((P, B, R, 7), np.float32)
+        targets = np.zeros((P, B, R, 4))
+        for p in range(P):
+            for b in range(B):
+                if kind == 0:
+                    u = np.concatenate([_u24(seed, (p, 2 * b, 0, 2)), _u24(seed, (p, 2 * b + 1, 0, 2))])[:7]
+                    s0 = np.clip(prob.q_home + pr.ik_noise * (2 * u - 1), prob.lo, prob.hi)
+                    sub, first = 2 * b, s0
+                    targets[p, b] = prob.block_init[b]
+                else:
+                    sub, first = 2 * B + 2 * b, qg32[p, b]
+                    targets[p, b] = pose[p, b]
+                starts[p, b] = _lift_starts(prob, pr, seed, p, sub, first)
+                fused[p, b] = _lift_starts(prob, pr, seed, p, sub, first, fused=True)
+        q32, q64, stable = _ik_runs(sp, dev, o, prob, pr, kind, targets.reshape(-1, 4), starts.reshape(-1, 7))
+        tf = T(fused.reshape(-1, 7))
+        dev.ik_iterate(kind, T(targets.reshape(-1, 4)), tf, pr.ik_iters)
+        q32f = N(tf).reshape(P, B, R, 7)
+        err64 = np.array([o.ik_error(kind, t, q) for t, q in zip(targets.reshape(-1, 4), q64)])
+        keep = stable & (err64 < 1e-4)
+        d = np.abs(q32 - q64).max(axis=1)
+        compared += int(keep.sum())
+        worst = max(worst, float(d[keep].max()) if keep.any() else 0.0)
+        report(f"ik lift kind{kind}", converged=float((err64 < 1e-4).mean()), compared=float(keep.mean()),
+               worst_rad=float(d[keep].max()) if keep.any() else 0.0,
+               p99_rad=float(np.percentile(d[keep], 99)) if keep.any() else 0.0)
+        assert keep.mean() > 0.08
+        # per-iteration rounding is not a start perturbation: a few kept starts still
+        # drift, so the bound is on the 95th percentile and the largest is reported
+        assert np.percentile(d[keep], 95) <= 1e-4, np.sort(d[keep])[-8:]
+        q32 = q32.reshape(P, B, R, 7)
+        chosen = qg32 if kind == 0 else qp32
+        for p in range(P):
+            for b in range(B):
+                # the device's starts are one of two roundings (product then sum, or fused);
+                # the lift runs the same iteration code as the single-iteration entry point,
+                # so the chosen configuration is bit for bit one start's solution of one
+                # variant, and that start is one the rule allows
+                ok = False
+                for var in (q32[p, b], q32f[p, b]):
+                    hit = [r for r in range(R) if np.array_equal(chosen[p, b], var[r])]
+                    if hit:
+                        cand = _pick_candidates(o, kind, targets[p, b], var.astype(np.float64), pose[p], b)
+                        ok = ok or bool(set(hit) & set(cand.tolist()))
+                assert ok, (kind, p, b)
+                picked += 1
+    report("ik lift", starts_compared=compared, worst_rad=worst, choices=picked)
 
 
 def test_traj_init_parity(sp, orc):
@@ -576,3 +686,41 @@ def test_solve_ttfs(sp):
         if rt["success"]:
             assert rt["viol"] < pr.sat_eps and rt["n_sat"] > 0
         assert bool(torch.isfinite(tq).all())
+
+
+def test_solve_ttfs_stops_where_the_oracle_does(sp, orc):
+    """The device-decided early exit: the returned particle equals the plain chunked
+    descent run to the stopping iteration (bit for bit), the oracle confirms that it
+    satisfies the constraints there, and that no particle did at the previous check."""
+    checked = 0
+    for s in synth.certified_seeds("tower4")[:6]:
+        prob, pr, cfg = synth.config("tower4", s)
+        cfg = dataclasses.replace(cfg, N1=1024, M=128)
+        dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+        every = 20
+        rt, tq, tp = dev.solve_ttfs(cfg, check_every=every, max_attempts=1)
+        stop = rt["iters"]
+        report(f"ttfs tower4 scene {s}", success=rt["success"], iters=stop, viol=rt["viol"], ms=rt["total_ms"])
+        assert rt["attempts"] == 1 and (stop % every == 0 or stop == cfg.K)
+        pose, _, _, _ = dev.stage1(cfg.N1, cfg.M, cfg.seed)
+        qg, qp = dev.ik_lift(pose, cfg.seed)
+        q = dev.traj_init(qg, qp, cfg.W, cfg.seed, pose)
+        opt = dev.opt_state(cfg.M, cfg.W)
+        prev = None
+        if stop > every:
+            dev.traj_optimize(q, pose, opt, 1, stop - every + 1, cfg.K, want_cost=False)
+            prev = (N(q), N(pose))
+            c, v = dev.traj_optimize(q, pose, opt, stop - every + 1, stop + 1, cfg.K)
+        else:
+            c, v = dev.traj_optimize(q, pose, opt, 1, stop + 1, cfg.K)
+        best = int(N(sp.order(c, v, pr.sat_eps)[0])[0])
+        assert torch.equal(tq, q[best]) and torch.equal(tp, pose[best])
+        if not rt["success"]:
+            continue
+        checked += 1
+        _, v64, *_ = o.traj_cost(N(tq)[None], N(tp)[None], orc.QUAD, grad=False)
+        assert v64[0] < pr.sat_eps + 1e-5
+        if prev is not None:
+            _, v64, *_ = o.traj_cost(prev[0], prev[1], orc.QUAD, grad=False)
+            assert v64.min() >= pr.sat_eps - 1e-5
+    assert checked >= 2

@@ -540,6 +540,106 @@ def test_schedule_alg1(orc):
             assert ph == orc.QUAD and lr == 0.003
 
 
+def _stage1_by_steps(o, pr, N, M, seed, rnd):
+    """Alg. 1 lines 1-14 spelled out from the separately pinned primitives: sample N,
+    linear cost, stable ascending sort, keep M, K_lin linear-phase then K_quad
+    quadratic-phase descent steps, final quadratic evaluation."""
+    x = o.sample(N, seed, rnd)
+    c, _, _, _ = o.place_cost(x, orc_lin(o))
+    xs = x[np.argsort(c, kind="stable")[:M]]
+    for k in range(1, pr.k_lin1 + pr.k_quad1 + 1):
+        phase, lr = o.schedule(k, pr.k_lin1, pr.eta1, pr.alpha1)
+        _, _, g, _ = o.place_cost(xs, phase)
+        xs = o.gd_step(xs, g, lr)
+    c, v, _, _ = o.place_cost(xs, 1 - orc_lin(o))
+    return xs, c, v
+
+
+def orc_lin(o):
+    import oracle
+    return oracle.LIN
+
+
+# stage-1 schedules that make satisfying placements rare on the 4-block tower: one
+# quadratic step after a zero-length linear phase (no round satisfies), or a short one
+# (the first round of some scenes has no satisfying particle, later rounds do)
+NO_SAT = dict(k_lin1=1, k_quad1=1, alpha1=0.5)
+RARE_SAT = dict(k_lin1=2, k_quad1=1, alpha1=0.1)
+
+
+@pytest.mark.parametrize("sched", [None, NO_SAT, RARE_SAT])
+def test_stage1_is_alg1_composition(orc, sched):
+    import dataclasses
+    prob, pr, _ = synth.config("tower4", synth.certified_seeds("tower4")[0])
+    if sched:
+        pr = dataclasses.replace(pr, **sched)
+    o = orc.Oracle(prob, pr)
+    for N, M, rnd in [(64, 8, 0), (300, 17, 2), (16, 16, 1)]:
+        x, c, v = o.stage1(N, M, seed=3, rnd=rnd)
+        xr, cr, vr = _stage1_by_steps(o, pr, N, M, 3, rnd)
+        assert np.array_equal(x, xr) and np.array_equal(c, cr) and np.array_equal(v, vr), (N, M, rnd)
+
+
+@pytest.mark.parametrize("sched,seed,expect_rounds", [(RARE_SAT, 0, 2), (NO_SAT, 0, 5), (None, 0, 1)])
+def test_solve_tower_branch_is_alg1(orc, sched, seed, expect_rounds):
+    """The tower branch of the whole FP64 solve, rebuilt from the pinned pieces: stage-1
+    rounds until one has a satisfying particle (at most retries + 1 rounds; the last
+    round is lifted when none does), satisfying-first order, z at the slot heights, lift,
+    seeding, K Adam iterations, final quadratic evaluation and order."""
+    import dataclasses
+    s0 = synth.certified_seeds("tower4")[seed]
+    prob, pr, _ = synth.config("tower4", s0)
+    if sched:
+        pr = dataclasses.replace(pr, **sched)
+    o = orc.Oracle(prob, pr)
+    cfg = synth.SolveConfig(N1=64, M=8, W=6, K=6, seed=3)
+    res = o.solve(cfg)
+    for rnd in range(pr.retries + 1):
+        xs, c, v = _stage1_by_steps(o, pr, cfg.N1, cfg.M, cfg.seed, rnd)
+        key = np.lexsort((np.arange(cfg.M), c, v >= pr.sat_eps))
+        nsat = int(np.sum(v < pr.sat_eps))
+        if nsat > 0:
+            break
+    assert res["rounds"] == rnd + 1 == expect_rounds and res["stage1_sat"] == nsat
+    pose = np.zeros((cfg.M, prob.B, 4))
+    pose[..., [0, 1, 3]] = xs[key]
+    pose[..., 2] = (np.arange(prob.B) + 0.5) * prob.h
+    assert np.array_equal(res["pose0"], pose)
+    qg, qp = o.ik_lift(pose, cfg.seed)
+    q = o.traj_init(qg, qp, cfg.W, cfg.seed, pose)
+    mq, vq, mp, vp = np.zeros_like(q), np.zeros_like(q), np.zeros_like(pose), np.zeros_like(pose)
+    for k in range(1, cfg.K + 1):
+        phase, lr = o.schedule(k, pr.k_lin2(cfg.K), pr.eta2, pr.alpha2)
+        _, _, gq, gp, _, _ = o.traj_cost(q, pose, phase)
+        q, pose, mq, vq, mp, vp = o.adam_step(q, pose, mq, vq, mp, vp, gq, gp, lr, k)
+    cost, viol = o.traj_cost(q, pose, 1 - orc_lin(o), grad=False)[:2]
+    assert np.array_equal(res["q"], q) and np.array_equal(res["pose"], pose)
+    assert np.array_equal(res["viol"], viol) and np.array_equal(res["cost"], cost)
+    key2 = np.lexsort((np.arange(cfg.M), cost, viol >= pr.sat_eps))
+    assert res["best"] == key2[0] and res["n_sat"] == int(np.sum(viol < pr.sat_eps))
+    assert res["success"] == (res["n_sat"] > 0)
+
+
+def test_residual_breakdown_is_the_violation(orc):
+    """The per-kind residual breakdown (a diagnostic) takes the violation apart: its
+    maximum is the quadratic-phase violation, the placement entry is the placement cost's
+    violation of the pose variables, and a scene without boxes has no box residuals."""
+    import dataclasses
+    rng = np.random.default_rng(31)
+    for name, W in (("tower4", 8), ("tiny", 16)):
+        prob, pr, _ = synth.config(name, synth.certified_seeds(name)[0])
+        o = orc.Oracle(prob, pr)
+        q, pose = synth.random_states(rng, prob, 6, W)
+        cat = o.traj_residuals(q, pose)
+        _, v, _, _, _, _ = o.traj_cost(q, pose, orc.QUAD, grad=False)
+        assert np.array_equal(cat.max(axis=1), v)
+        if prob.mode == synth.MODE_TOWER:
+            assert np.array_equal(cat[:, 7], o.place_cost(pose, orc.QUAD, grad=False)[1])
+        o0 = orc.Oracle(dataclasses.replace(prob, boxes=np.zeros((0, 6))), pr)
+        cat0 = o0.traj_residuals(q, pose)
+        assert np.all(cat0[:, [0, 2]] == 0) and np.array_equal(cat0[:, 4:7], cat[:, 4:7])
+
+
 def test_gd_step_clamp(orc):
     prob, pr, _ = synth.config("tower4", 0)
     o = orc.Oracle(prob, pr)
@@ -558,7 +658,8 @@ def test_gd_step_clamp(orc):
 
 def test_adam_matches_torch(orc):
     """Three Adam steps: torch.optim.Adam (FP64) with the boundary copies fed the sum of
-    their gradients."""
+    their gradients and the start configuration held (a zero gradient from the first
+    step leaves torch's Adam in place)."""
     import torch
     rng = np.random.default_rng(15)
     prob, pr, _ = synth.config("tower4", 0)
@@ -581,6 +682,7 @@ def test_adam_matches_torch(orc):
         s = g[:, :-1, W - 1] + g[:, 1:, 0]
         g[:, :-1, W - 1] = s
         g[:, 1:, 0] = s
+        g[:, 0, 0] = 0.0
         for grp in opt.param_groups:
             grp["lr"] = lr
         tq.grad = torch.tensor(g)
@@ -1055,6 +1157,24 @@ def test_p2p_adam_pins_endpoints(orc):
     q2, _ = o.stage2(q, pose, 20)
     assert np.array_equal(q2[:, 0, 0], q[:, 0, 0]) and np.array_equal(q2[:, 0, -1], q[:, 0, -1])
     assert np.all(np.abs(q2[:, 0, 1:-1] - q[:, 0, 1:-1]).max(axis=(1, 2)) > 0)
+
+
+def test_tower_adam_pins_start(orc):
+    """The first configuration of a tower trajectory stays at q_home through stage 2 (the
+    robot starts there), while every other waypoint moves."""
+    prob, pr, _ = synth.config("tower4", synth.certified_seeds("tower4")[0])
+    o = orc.Oracle(prob, pr)
+    rng = np.random.default_rng(43)
+    x = synth.clustered_placements(rng, prob, 3, spread=0.01)
+    pose = o.initial_poses(x)
+    qg, qp = o.ik_lift(pose, seed=1)
+    q = o.traj_init(qg, qp, 8, seed=1, pose=pose)
+    assert np.array_equal(q[:, 0, 0], np.broadcast_to(np.clip(prob.q_home, prob.lo, prob.hi), (3, 7)))
+    q2, _ = o.stage2(q, pose, 10)
+    assert np.array_equal(q2[:, 0, 0], q[:, 0, 0])
+    moved = np.abs(q2 - q).max(axis=-1)
+    moved[:, 0, 0] = 1.0
+    assert np.all(moved > 0)
 
 
 def _philox24(seed, ctr):
