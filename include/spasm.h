@@ -230,6 +230,18 @@ size_t spasm_select_topm_workspace(int32_t N, int32_t M);
 int spasm_select_topm_large(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *d_work,
                             size_t work_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the selection of
+ * spasm_select_topm_large without a workspace.  Its scratch (the select state, histogram,
+ * per-range counts and survivors) is one static device array per GPU of
+ * spasm_select_topm_static_bytes() bytes (about 74 KB, held until the process ends),
+ * enough for every supported shape: 1 <= M <= N <= 2^20, M <= 8192 when N > 16384; larger
+ * sizes return SPASM_EUNSUPPORTED.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); each call resets the scratch it reads.  Calls that overlap
+ * on one GPU (concurrent streams or threads) share that array and race: serialise them. */
+size_t spasm_select_topm_static_bytes(void);
+int spasm_select_topm_static(int32_t N, const float *d_key, int32_t M, int32_t *d_idx, void *stream);
+
 /* Alg. 1 GetSatisfyingParticles + re-evaluated ArgSort: order of all n particles with the
  * satisfying ones (viol < eps) first, each group by cost then index; d_nsat [1] int32
  * receives the number of satisfying particles.  n <= 16384. */

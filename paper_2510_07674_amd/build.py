@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspasm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "serve.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "serve.hip", "noalloc.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

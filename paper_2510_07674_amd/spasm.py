@@ -69,6 +69,8 @@ SYMBOLS = {
     "spasm_order": ([c_i32, c_vp, c_vp, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
     "spasm_select_topm_workspace": ([c_i32, c_i32], ctypes.c_size_t),
     "spasm_select_topm_large": ([c_i32, c_vp, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp], c_i32),
+    "spasm_select_topm_static_bytes": ([], ctypes.c_size_t),
+    "spasm_select_topm_static": ([c_i32, c_vp, c_i32, c_vp, c_vp], c_i32),
     "spasm_place_workspace": ([c_vp, c_i32, c_i32], ctypes.c_size_t),
     "spasm_place_round": ([c_vp, c_i32, c_i32, c_u64, c_i32, c_vp, ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp, c_vp],
                           c_i32),

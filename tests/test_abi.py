@@ -231,3 +231,16 @@ def test_problem_create_rejects_mode_options(mutate):
         a["pr"].al_rho = math.nan
     rc, msg = _create(a)
     assert rc == -1 and msg, (rc, msg)
+
+
+def test_static_topm_size_checks():
+    """The allocation-free selection refuses shapes beyond its static scratch on the host;
+    the scratch holds the largest workspace the radix select can ask for."""
+    from paper_2510_07674_amd import spasm
+    L = spasm.load()
+    dummy = ctypes.c_void_p(256)
+    assert L.spasm_select_topm_static((1 << 20) + 1, dummy, 8, dummy, None) == -4
+    assert L.spasm_select_topm_static(20000, dummy, 8193, dummy, None) == -4
+    assert L.spasm_select_topm_static(100, dummy, 101, dummy, None) == -1
+    assert L.spasm_select_topm_static(100, None, 10, dummy, None) == -1
+    assert L.spasm_select_topm_static_bytes() == L.spasm_select_topm_workspace(1 << 20, 8192)
