@@ -1363,8 +1363,12 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
     }
 }
 
-template <int MODE, int CH>
-__global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
+// BOUND: the launch bound the registers are allocated for -- 1024 threads (128 VGPRs, 16
+// waves per CU) or 768 (168 VGPRs, 12 waves per CU; fewer spills).  The optimisation
+// launch takes 768 when a CU holds as many of its particles either way (6 or 9-12 waves
+// per particle, e.g. a 10-block tower: one particle per CU).
+template <int MODE, int CH, int BOUND = 1024>
+__global__ __launch_bounds__(BOUND) void k_traj(KProb P, TrajArgs a)
 {
     extern __shared__ float s_mv[];
     if (a.skip && __builtin_amdgcn_readfirstlane(*a.skip)) return;
@@ -1376,8 +1380,8 @@ __global__ __launch_bounds__(1024) void k_traj(KProb P, TrajArgs a)
 // read through the constant address space so that their fields stay in scalar registers.
 typedef __attribute__((address_space(4))) const char cchar;
 
-template <int CH>
-__global__ __launch_bounds__(1024) void k_serve(const ServeSolve *solves, int nsolve)
+template <int CH, int BOUND>
+__global__ __launch_bounds__(BOUND) void k_serve(const ServeSolve *solves, int nsolve)
 {
     extern __shared__ float s_mv[];
     cchar *base = (cchar *)solves;
@@ -2178,6 +2182,13 @@ hipError_t launch_place(const KProb &P, int n, const float *x_in, const int32_t 
 
 int traj_threads(int B, int W) { return ((2 * B * W + 63) / 64) * 64; }
 
+// The optimisation launch's register bound for particles of `threads` lanes (see k_traj).
+static bool opt_bound_768(int threads)
+{
+    const int w = threads / 64;
+    return w <= 12 && 12 / w == 16 / w;
+}
+
 template <int CH>
 static hipError_t launch_traj_ch(const KProb &P, int mode, const TrajArgs &a, hipStream_t st)
 {
@@ -2186,6 +2197,9 @@ static hipError_t launch_traj_ch(const KProb &P, int mode, const TrajArgs &a, hi
         hipLaunchKernelGGL((k_traj<0, CH>), dim3(a.P), dim3(threads), 0, st, P, a);
     else if (mode == 1)
         hipLaunchKernelGGL((k_traj<1, CH>), dim3(a.P), dim3(threads), 0, st, P, a);
+    else if (opt_bound_768(threads))
+        hipLaunchKernelGGL((k_traj<2, CH, 768>), dim3(a.P), dim3(threads), (size_t)2 * NJ * threads * sizeof(float),
+                           st, P, a);
     else
         hipLaunchKernelGGL((k_traj<2, CH>), dim3(a.P), dim3(threads), (size_t)2 * NJ * threads * sizeof(float), st,
                            P, a);
@@ -2204,14 +2218,25 @@ hipError_t launch_traj(const KProb &P, int mode, const TrajArgs &a, hipStream_t 
     }
 }
 
+template <int CH>
+static void launch_serve_ch(int threads, int nwg, const ServeSolve *d_solves, int nsolve, hipStream_t st)
+{
+    // the same register bound as the plain optimisation launch of this shape, so that a
+    // served particle runs the same instructions
+    const size_t shm = (size_t)2 * NJ * threads * sizeof(float);
+    if (opt_bound_768(threads))
+        hipLaunchKernelGGL((k_serve<CH, 768>), dim3(nwg), dim3(threads), shm, st, d_solves, nsolve);
+    else
+        hipLaunchKernelGGL((k_serve<CH, 1024>), dim3(nwg), dim3(threads), shm, st, d_solves, nsolve);
+}
+
 hipError_t launch_serve(int chunk, int threads, int nwg, const ServeSolve *d_solves, int nsolve, hipStream_t st)
 {
-    const size_t shm = (size_t)2 * NJ * threads * sizeof(float);
     switch (chunk) {
-    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
-    case 6: hipLaunchKernelGGL(k_serve<6>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
-    case 7: hipLaunchKernelGGL(k_serve<7>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
-    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(nwg), dim3(threads), shm, st, d_solves, nsolve); break;
+    case 4: launch_serve_ch<4>(threads, nwg, d_solves, nsolve, st); break;
+    case 6: launch_serve_ch<6>(threads, nwg, d_solves, nsolve, st); break;
+    case 7: launch_serve_ch<7>(threads, nwg, d_solves, nsolve, st); break;
+    case 8: launch_serve_ch<8>(threads, nwg, d_solves, nsolve, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2225,7 +2250,14 @@ hipError_t set_smem_limits(size_t sort_bytes, size_t traj_bytes)
 #define SPASM_TRAJ_ATTR(CH)                                                                                      \
     e = hipFuncSetAttribute((const void *)k_traj<2, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
     if (e != hipSuccess) return e;                                                                           \
-    e = hipFuncSetAttribute((const void *)k_serve<CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)traj_bytes); \
+    e = hipFuncSetAttribute((const void *)k_traj<2, CH, 768>, hipFuncAttributeMaxDynamicSharedMemorySize,     \
+                            (int)traj_bytes);                                                                \
+    if (e != hipSuccess) return e;                                                                           \
+    e = hipFuncSetAttribute((const void *)k_serve<CH, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                            (int)traj_bytes);                                                                \
+    if (e != hipSuccess) return e;                                                                           \
+    e = hipFuncSetAttribute((const void *)k_serve<CH, 768>, hipFuncAttributeMaxDynamicSharedMemorySize,       \
+                            (int)traj_bytes);                                                                \
     if (e != hipSuccess) return e;
     SPASM_TRAJ_ATTR(4)
     SPASM_TRAJ_ATTR(6)

@@ -78,11 +78,13 @@ def test_result_same_alone_and_in_mix(sp):
         assert res["viol"] == mixed[i]["result"]["viol"] and res["n_sat"] == mixed[i]["result"]["n_sat"]
 
 
-def test_reordered_plain_solve_equals_served(sp):
-    """1024 particles of 5 waves do not all fit on the chip at once, so the plain solve
-    launches them costliest first, while the serving launch takes them in natural order;
-    every particle computes the same on any workgroup, so the results are identical."""
-    dev, cfg = _req(sp, 7, 5, 30, 32, 1024, 30)
+@pytest.mark.parametrize("B,M", [(5, 1024), (10, 512)])
+def test_reordered_plain_solve_equals_served(sp, B, M):
+    """1024 particles of 5 waves (or 512 of 10 waves, whose launches take the 768-thread
+    register bound) do not all fit on the chip at once, so the plain solve launches them
+    costliest first, while the serving launch takes them in natural order; every particle
+    computes the same on any workgroup, so the results are identical."""
+    dev, cfg = _req(sp, 7, B, 30, 32, M, 30)
     srv = sp.Server(2 << 30, max_slots=4, iters_per_step=10)
     srv.submit(dev, cfg, 0)
     out = _drain(srv)
