@@ -36,18 +36,22 @@ def flop_per_eval(S, O, B, W):
 def stored_counters(workload):
     """Machine-readable lines of the committed counter summary of the fused stage-2 kernel
     on this workload (profiles/k_traj_<workload>_counters.md), or None when there is none
-    or the kernel source has changed since the counters were taken."""
+    or the kernel source or the build flags have changed since the counters were taken
+    (the hash covers kernels.hip followed by build.py)."""
     import hashlib
     summary = os.path.join(ROOT, "profiles", f"k_traj_{workload}_counters.md")
-    src = os.path.join(ROOT, "paper_2510_07674_amd", "csrc", "kernels.hip")
+    pkg = os.path.join(ROOT, "paper_2510_07674_amd")
     try:
         fields = {}
         for line in open(summary):
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip()
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in (os.path.join(pkg, "csrc", "kernels.hip"), os.path.join(pkg, "build.py")):
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
     except OSError:
         return None
     if fields.get("kernels_sha256") != sha or fields.get("workload") != workload:

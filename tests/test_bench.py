@@ -31,24 +31,35 @@ def test_flop_per_eval_tower4():
     assert bench.flop_per_eval(42, 40, 5, 32) > base
 
 
-def _summary_fields():
+def _summary_fields(workload):
     fields = {}
-    for line in open(os.path.join(ROOT, "profiles", "k_traj_tower4_counters.md")):
+    for line in open(os.path.join(ROOT, "profiles", f"k_traj_{workload}_counters.md")):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
     return fields
 
 
+def _source_hash():
+    h = hashlib.sha256()
+    for name in (("csrc", "kernels.hip"), ("build.py",)):
+        with open(os.path.join(ROOT, "paper_2510_07674_amd", *name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def test_stored_traffic_is_gated():
-    fields = _summary_fields()
-    assert fields["workload"] == "tower4"
-    for other in ("tower10", "tiny", "p2p"):
-        assert bench.stored_traffic(other) is None
-    with open(os.path.join(ROOT, "paper_2510_07674_amd", "csrc", "kernels.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    got = bench.stored_traffic("tower4")
-    if sha == fields["kernels_sha256"]:
-        assert got == float(fields["traffic_bytes_per_launch"])
-    else:
-        assert got is None
+    """Counter figures are reported only for the workload they were taken on, and only
+    while the kernel source and build flags hash to the recorded value."""
+    for other in ("tiny", "p2p"):
+        assert bench.stored_traffic(other) is None and bench.stored_executed_flop(other) is None
+    sha = _source_hash()
+    for workload in ("tower4", "tower10"):
+        fields = _summary_fields(workload)
+        assert fields["workload"] == workload
+        got, flop = bench.stored_traffic(workload), bench.stored_executed_flop(workload)
+        if sha == fields["kernels_sha256"]:
+            assert got == float(fields["traffic_bytes_per_launch"])
+            assert flop == float(fields["executed_fp32_flop_per_launch"])
+        else:
+            assert got is None and flop is None
