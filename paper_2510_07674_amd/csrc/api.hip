@@ -241,8 +241,9 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     const size_t off_init = align256((off_box + n_boxf) * 4) / 4;
     const size_t off_goal = align256((off_init + init.size()) * 4) / 4;
     const size_t off_cells = align256((off_goal + goal.size()) * 4) / 4;
-    const size_t total = align256((off_cells + cells.size()) * 4);
-    std::vector<float> host(total / 4, 0.f);
+    const size_t tables = align256((off_cells + cells.size()) * 4);
+    const size_t total = tables + align256(sizeof(KProb));  // then the problem struct itself
+    std::vector<float> host(tables / 4, 0.f);
     std::copy(sph.begin(), sph.end(), host.begin() + off_sph);
     std::copy(box.begin(), box.end(), host.begin() + off_box);
     std::copy(init.begin(), init.end(), host.begin() + off_init);
@@ -258,7 +259,7 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
         delete pb;
         return fail(SPASM_ENOMEM, "hipMalloc(%zu) failed", total);
     }
-    if (hipMemcpy(pb->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(pb->dmem, host.data(), tables, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(pb->dmem);
         delete pb;
         return fail(SPASM_EHIP, "problem upload failed");
@@ -279,6 +280,7 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     K.blk_init = (const float4 *)(base + off_init);
     K.goal = (const float4 *)(base + off_goal);
     K.cells = (const float4 *)(base + off_cells);
+    K.self = (const KProb *)((char *)pb->dmem + tables);
     K.yaw_steps = skel->sample_yaw_steps;
     K.lpb_log2 = 3;
     if (skel->mode == SPASM_MODE_PACK) {  // one lane per cell of the largest piece, at least 4
@@ -351,6 +353,10 @@ extern "C" int spasm_problem_create(const spasm_chain_desc *chain, int32_t n_sph
     pb->lin_frac2 = prm->lin_frac2;
     pb->sat_eps = (float)prm->sat_eps;
     pb->ik_iters = prm->ik_iters;
+    if (hipMemcpy((void *)K.self, &K, sizeof(KProb), hipMemcpyHostToDevice) != hipSuccess) {
+        spasm_problem_destroy(pb);
+        return fail(SPASM_EHIP, "problem upload failed");
+    }
     *out = pb;
     return SPASM_OK;
 }

@@ -1675,7 +1675,9 @@ __global__ void k_gather_place(int B, int M, const float *xs, const float *cs, c
 // IK error of the block frame T_B = T_E G^-1 at q (position, then orientation: kind 0
 // the z axis against e_z, kind 1 half the sum of axis cross products against Rz(yaw)),
 // with the joint origins and axes o_{j-1}, z_{j-1} and the block origin for the Jacobian.
-__device__ __forceinline__ void ik_eval(const KProb &P, int kind, float tx, float ty, float tz, float cy, float sy,
+// P: the problem by reference (KProb) or through the constant address space (cKProb).
+template <class KP>
+__device__ __forceinline__ void ik_eval(const KP &P, int kind, float tx, float ty, float tz, float cy, float sy,
                                         const float (&q)[NJ], float (&ax)[NJ][6], float &t0, float &t1, float &t2,
                                         float (&e)[6])
 {
@@ -1688,7 +1690,7 @@ __device__ __forceinline__ void ik_eval(const KProb &P, int kind, float tx, floa
         dh_step(F, P.a[j], P.d[j], P.ca[j], P.sa[j], q[j]);
     }
     const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
-    const float *Gr = P.Gi_R;
+    const auto &Gr = P.Gi_R;
     float RB[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1725,7 +1727,8 @@ __device__ __forceinline__ void ik_eval(const KProb &P, int kind, float tx, floa
     }
 }
 
-__device__ __forceinline__ float ik_error(const KProb &P, int kind, float tx, float ty, float tz, float tyaw,
+template <class KP>
+__device__ __forceinline__ float ik_error(const KP &P, int kind, float tx, float ty, float tz, float tyaw,
                                           const float (&q)[NJ])
 {
     float sy, cy;
@@ -1740,10 +1743,14 @@ __device__ __forceinline__ float ik_error(const KProb &P, int kind, float tx, fl
 
 // Not inlined: the single-iteration entry point and the multi-start lift then run the
 // same instructions, so their iterates are bit-identical (inlined copies may contract
-// multiply-adds differently once `kind` is a constant).
-__device__ __noinline__ void ik_run(const KProb &P, int kind, float tx, float ty, float tz, float tyaw, float (&q)[NJ],
-                                    int iters)
+// multiply-adds differently once `kind` is a constant).  The problem comes as its device
+// copy in the constant address space: a reference to the kernel's by-value argument
+// would make every lane copy the whole struct to scratch memory.
+typedef __attribute__((address_space(4))) const KProb cKProb;
+__device__ __noinline__ void ik_run(const cKProb *Pc, int kind, float tx, float ty, float tz, float tyaw,
+                                    float (&q)[NJ], int iters)
 {
+    const cKProb &P = *Pc;
     float sy, cy;
     sincosf(tyaw, &sy, &cy);
     const float lam2 = P.ik_lambda * P.ik_lambda;
@@ -1821,7 +1828,7 @@ __global__ void k_ik_iterate(KProb P, int kind, int n, const float *target, floa
 #pragma unroll
     for (int j = 0; j < NJ; ++j) q[j] = qio[(size_t)gid * NJ + j];
     const float *t = target + (size_t)gid * 4;
-    ik_run(P, kind, t[0], t[1], t[2], t[3], q, iters);
+    ik_run((const cKProb *)P.self, kind, t[0], t[1], t[2], t[3], q, iters);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qio[(size_t)gid * NJ + j] = q[j];
 }
@@ -1921,7 +1928,7 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     const float4 I = ldc(P.blk_init, 2 * b);
     float err = INFINITY, pen = 0.f;
     if (r < R) {
-        ik_run(P, 0, I.x, I.y, I.z, 0.f, q, iters);
+        ik_run((const cKProb *)P.self, 0, I.x, I.y, I.z, 0.f, q, iters);
         err = ik_error(P, 0, I.x, I.y, I.z, 0.f, q);
         if (err < 1e-4f) pen = arm_clutter(P, q, pose + (size_t)p * B * 4, b, 0);
     }
@@ -1941,7 +1948,7 @@ __global__ __launch_bounds__(256) void k_ik_lift(KProb P, int nP, const float *p
     err = INFINITY;
     pen = 0.f;
     if (r < R) {
-        ik_run(P, 1, t[0], t[1], t[2], t[3], q, iters);
+        ik_run((const cKProb *)P.self, 1, t[0], t[1], t[2], t[3], q, iters);
         err = ik_error(P, 1, t[0], t[1], t[2], t[3], q);
         if (err < 1e-4f) pen = arm_clutter(P, q, pose + (size_t)p * B * 4, b, 1);
     }

@@ -25,6 +25,7 @@ struct KProb {
     const float4 *blk_init;  // [B][2] (x, y, z, yaw), (cos yaw, sin yaw, 0, 0)
     const float4 *goal;      // [B][2] same layout (fixed goals)
     const float4 *cells;     // [B][8] packing cells (ox, oy, 1, 0); (0, 0, 0, 0) past a piece's last cell
+    const KProb *self;       // this struct's copy in device memory (for non-inlined device functions)
     int B, S, O, mode;
     int yaw_steps;           // stage-1 yaw samples on yaw_steps directions (0: uniform)
     int lpb_log2;            // stage-1 lanes per block: 8 block spheres (3); packing: cells rounded up to 2^k >= 4
