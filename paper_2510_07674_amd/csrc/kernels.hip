@@ -94,6 +94,16 @@ __device__ __forceinline__ float lane_prev(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
+// within each 32-lane half of the wave
+template <class Op>
+__device__ __forceinline__ float half_reduce(float v, Op op)
+{
+    v = group8_reduce(v, op);
+    v = op(v, dpp<0x140>(v));  // row_mirror
+    const int c = __float_as_int(v);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(c, c, false, false);
+    return op(__int_as_float(s16[0]), __int_as_float(s16[1]));
+}
 __device__ __forceinline__ float wave_sum(float v) { return wave_reduce(v, OpSum()); }
 __device__ __forceinline__ float wave_min(float v) { return wave_reduce(v, OpMin()); }
 __device__ __forceinline__ float wave_max(float v) { return wave_reduce(v, OpMax()); }
@@ -271,15 +281,26 @@ __device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (
 __shared__ int s_wave_work[16];
 constexpr int PRIO_STEP = 48;  // narrow-phase passes per priority level (levels 0..3)
 
-template <bool GRAD, int CH>
+template <bool GRAD, int CH, bool HB = false>
 __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
                                               const float (&cy)[CH], const float (&cz)[CH], const float (&r)[CH],
                                               const LaneBox &lb, bool act, float &cost, float &viol, float (&wf)[3],
                                               float (&wt)[3])
 {
-    const float lo0 = uniform(wave_min(lb.lo0)), lo1 = uniform(wave_min(lb.lo1)), lo2 = uniform(wave_min(lb.lo2));
-    const float hi0 = uniform(wave_max(lb.hi0)), hi1 = uniform(wave_max(lb.hi1)), hi2 = uniform(wave_max(lb.hi2));
     const int lane = threadIdx.x & 63;
+    // broad phase bounds: the wave's union (lo, hi) or, with HB, each half wave's (lo/hi of
+    // lanes 0-31, and a second set for lanes 32-63)
+    float lo0, lo1, lo2, hi0, hi1, hi2, mo0 = 0.f, mo1 = 0.f, mo2 = 0.f, mh0 = 0.f, mh1 = 0.f, mh2 = 0.f;
+    if constexpr (HB) {
+        const float a0 = half_reduce(lb.lo0, OpMin()), a1 = half_reduce(lb.lo1, OpMin()), a2 = half_reduce(lb.lo2, OpMin());
+        const float b0 = half_reduce(lb.hi0, OpMax()), b1 = half_reduce(lb.hi1, OpMax()), b2 = half_reduce(lb.hi2, OpMax());
+        auto rl = [](float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); };
+        lo0 = rl(a0, 0); lo1 = rl(a1, 0); lo2 = rl(a2, 0); hi0 = rl(b0, 0); hi1 = rl(b1, 0); hi2 = rl(b2, 0);
+        mo0 = rl(a0, 32); mo1 = rl(a1, 32); mo2 = rl(a2, 32); mh0 = rl(b0, 32); mh1 = rl(b1, 32); mh2 = rl(b2, 32);
+    } else {
+        lo0 = uniform(wave_min(lb.lo0)); lo1 = uniform(wave_min(lb.lo1)); lo2 = uniform(wave_min(lb.lo2));
+        hi0 = uniform(wave_max(lb.hi0)); hi1 = uniform(wave_max(lb.hi1)); hi2 = uniform(wave_max(lb.hi2));
+    }
     int nar = 0;  // wave-uniform
     for (int base = 0; base < P.O; base += 64) {
         const int ol = base + lane;
@@ -287,6 +308,8 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
         if (ol < P.O) {
             const float4 bl = ldc(P.box, 4 * ol + 2), bh = ldc(P.box, 4 * ol + 3);
             ov = (bl.x <= hi0) & (bh.x >= lo0) & (bl.y <= hi1) & (bh.y >= lo1) & (bl.z <= hi2) & (bh.z >= lo2);
+            if constexpr (HB)
+                ov |= (bl.x <= mh0) & (bh.x >= mo0) & (bl.y <= mh1) & (bh.y >= mo1) & (bl.z <= mh2) & (bh.z >= mo2);
         }
         unsigned long long m = __ballot(ov);
         while (m) {
@@ -851,7 +874,7 @@ __device__ __forceinline__ float screw_dot(const Frame &F, const float (&wr)[6])
 // origin, force); before link J+1's contacts are added, <xi_{J+1}, wr> is subtracted
 // from g[J].  After the pass, g[j] + <xi_{j+1}, total wrench> is the reverse-mode
 // gradient sum over links >= j+1 (second pass in slot_eval).
-template <int J, bool GRAD, int CH>
+template <int J, bool GRAD, int CH, bool HB>
 __device__ __forceinline__ void links_forward(const KProb &P, int phase, const Slot &sl, bool own_vis,
                                               const float (&q)[NJ], const float *s_pose, float *s_pacc, Frame &F,
                                               float &cost, float &viol, float (&g)[NJ], float (&wr)[6])
@@ -875,7 +898,7 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
             r[i] = sp.w;
         }
         const LaneBox lb = lane_box<CH>(cx, cy, cz, r, sl.active);
-        collide_boxes<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, cost, viol, wf, wt);
+        collide_boxes<GRAD, CH, HB>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, cost, viol, wf, wt);
         if (P.mode != SPASM_MODE_P2P)  // a point-to-point problem has no blocks
             collide_blocks<GRAD, CH>(P, phase, P.w[W_ARM], cx, cy, cz, r, lb, sl.active, sl.b, own_vis, s_pose,
                                      s_pacc, cost, viol, wf, wt);
@@ -883,7 +906,7 @@ __device__ __forceinline__ void links_forward(const KProb &P, int phase, const S
     wr[0] = wt[0]; wr[1] = wt[1]; wr[2] = wt[2];
     wr[3] = wf[0]; wr[4] = wf[1]; wr[5] = wf[2];
     if constexpr (J + 1 < NJ)
-        links_forward<J + 1, GRAD, CH>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
+        links_forward<J + 1, GRAD, CH, HB>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
 }
 
 template <int J>
@@ -912,7 +935,7 @@ struct AlState {
 // cost are added by the caller.  GRAD: g[7] receives dC/dq of this slot, the pose
 // gradient goes to the wave's LDS accumulator (arm/held contacts with placed blocks)
 // and to s_tiepose (tie term).
-template <bool GRAD, int CH>
+template <bool GRAD, int CH, bool HB>
 __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
                                           const float *s_pose, float *s_pacc, float *s_tiepose, float &cost,
                                           float &viol, float (&g)[NJ], const AlState &al)
@@ -921,7 +944,7 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
     float wr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     Frame F;
     frame_identity(F);
-    links_forward<0, GRAD, CH>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
+    links_forward<0, GRAD, CH, HB>(P, phase, sl, own_vis, q, s_pose, s_pacc, F, cost, viol, g, wr);
     float et[3] = {wr[0], wr[1], wr[2]}, ef[3] = {wr[3], wr[4], wr[5]};
     // end effector and the block frame T_B = T_E G^-1
     const float pe0 = F.p0 + P.tool_d * F.z0, pe1 = F.p1 + P.tool_d * F.z1, pe2 = F.p2 + P.tool_d * F.z2;
@@ -1074,12 +1097,12 @@ __device__ __forceinline__ void slot_eval(const KProb &P, int phase, const Slot 
 // Whole-particle evaluation shared by every stage-2 mode: slot terms, smoothness (lane
 // shuffles: a segment is W consecutive lanes inside one wave) and the placement cost of
 // the pose variables (lanes tid < 8B, one block sphere each).
-template <bool GRAD, int CH>
+template <bool GRAD, int CH, bool HB = false>
 __device__ __forceinline__ void particle_eval(const KProb &P, int phase, const Slot &sl, int W, const float (&q)[NJ],
                                               const float *s_pose, float *s_pacc_wave, float *s_tiepose,
                                               float *s_placeg, float &cost, float &viol, float (&g)[NJ], const AlState &al)
 {
-    slot_eval<GRAD, CH>(P, phase, sl, W, q, s_pose, s_pacc_wave, s_tiepose, cost, viol, g, al);
+    slot_eval<GRAD, CH, HB>(P, phase, sl, W, q, s_pose, s_pacc_wave, s_tiepose, cost, viol, g, al);
     const float w_s = P.w[W_SMOOTH];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -1137,7 +1160,7 @@ __device__ __forceinline__ float adam_update(float x, float &m, float &v, float 
 
 // One particle per workgroup.  MODE 0: cost, 1: cost + gradient (optionally scaled per
 // particle), 2: optimise.  s_mv: dynamic LDS, [2][NJ][blockDim.x] Adam moments (MODE 2).
-template <int MODE, int CH>
+template <int MODE, int CH, bool HB = false>
 __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a, int p, float *s_mv)
 {
     __shared__ float s_pose[2 * MAX_B * 8];
@@ -1236,7 +1259,8 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
             schedule(k, a.k_lin2, P.eta2, P.alpha2, phase, lr);
             float cost = 0.f, viol = 0.f, g[NJ] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             al.update = al.lam && P.al_every > 0 && k % P.al_every == 0;
-            particle_eval<true, CH>(P, phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g, al);
+            particle_eval<true, CH, HB>(P, phase, sl, W, q, s_pose, s_pacc_w, s_tiepose, s_placeg, cost, viol, g,
+                                        al);
             if (sl.active && sl.w == W - 1)
                 for (int j = 0; j < NJ; ++j) s_tie[0][sl.s][j] = g[j];
             if (sl.active && sl.w == 0)
@@ -1366,13 +1390,14 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
 // BOUND: the launch bound the registers are allocated for -- 1024 threads (128 VGPRs, 16
 // waves per CU) or 768 (168 VGPRs, 12 waves per CU; fewer spills).  The optimisation
 // launch takes 768 when a CU holds as many of its particles either way (6 or 9-12 waves
-// per particle, e.g. a 10-block tower: one particle per CU).
+// per particle, e.g. a 10-block tower: one particle per CU); those particles' obstacle
+// broad phase bounds each half wave (one segment of 32 waypoints) on its own.
 template <int MODE, int CH, int BOUND = 1024>
 __global__ __launch_bounds__(BOUND) void k_traj(KProb P, TrajArgs a)
 {
     extern __shared__ float s_mv[];
     if (a.skip && __builtin_amdgcn_readfirstlane(*a.skip)) return;
-    traj_particle<MODE, CH>(P, a, a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x, s_mv);
+    traj_particle<MODE, CH, BOUND == 768>(P, a, a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x, s_mv);
 }
 
 // Serving: one launch advances every active solve of one (thread count, sphere chunk)
@@ -1396,7 +1421,7 @@ __global__ __launch_bounds__(BOUND) void k_serve(const ServeSolve *solves, int n
             hi = mid - 1;
     }
     const ServeSolve &d = *(const ServeSolve *)(base + (size_t)lo * sizeof(ServeSolve));
-    traj_particle<2, CH>(d.P, d.a, wg - d.first, s_mv);
+    traj_particle<2, CH, BOUND == 768>(d.P, d.a, wg - d.first, s_mv);
 }
 
 // ------------------------------------------------------------------------------------
