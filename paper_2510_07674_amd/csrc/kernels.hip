@@ -278,8 +278,11 @@ __device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (
 // wave with the most contacts sets its particle's pace, and the launch ends with the
 // slowest particle; that wave takes a higher issue priority on its SIMD for the next
 // iteration (see traj_particle).
+// Narrow-phase passes per priority level (levels 0..3): 24 where a CU holds several
+// particles (their waves compete for the SIMDs), 8 for the particles of 9-12 waves that
+// have a CU to themselves (measured on 4- and 10-block towers).
 __shared__ int s_wave_work[16];
-constexpr int PRIO_STEP = 48;  // narrow-phase passes per priority level (levels 0..3)
+constexpr int PRIO_STEP = 24, PRIO_STEP_HB = 8;
 
 template <bool GRAD, int CH, bool HB = false>
 __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float wgt, const float (&cx)[CH],
@@ -1243,7 +1246,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                 // issue priority from the previous iteration's contact work: the waves
                 // that hold their particles back run first on their SIMDs (scheduling
                 // only; the arithmetic is the same)
-                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / PRIO_STEP;
+                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / (HB ? PRIO_STEP_HB : PRIO_STEP);
                 if (lane == 0) s_wave_work[wave] = 0;
                 if (lvl >= 3)
                     __builtin_amdgcn_s_setprio(3);
