@@ -156,3 +156,38 @@ def test_tower_solve_vs_oracle(sp, orc, k):
     both = (v32 >= pr.sat_eps) & (v64 >= pr.sat_eps)
     ratio = np.abs(np.log(v32[both] / v64[both])) if both.any() else np.zeros(1)
     assert np.mean(ratio <= np.log(2.0)) >= 0.8, np.sort(ratio)[-4:]
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_tower10_solve_vs_oracle(sp, orc, k):
+    """A small 10-block tower solve (80 boxes, 20 segments of 32 waypoints): the device
+    pipeline equals its pieces bit for bit, and from the device's stage-1, lift and
+    seeding state the FP64 oracle's K Adam iterations end in the same success flags (those
+    within 1e-5 of the threshold aside) and, where both stay infeasible, violations within
+    a factor 2 for at least 80 % of the particles."""
+    prob, pr, _ = synth.config("tower10", synth.certified_seeds("tower10")[k])
+    cfg = synth.SolveConfig(N1=2048, M=32, W=32, K=300, seed=11)
+    dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
+    res, bq, bp = dev.solve(cfg)
+    pose, _, _, info = dev.stage1(cfg.N1, cfg.M, cfg.seed)
+    qg, qp = dev.ik_lift(pose, cfg.seed)
+    q = dev.traj_init(qg, qp, cfg.W, cfg.seed, pose)
+    q0, p0 = N(q), N(pose)
+    opt = dev.opt_state(cfg.M, cfg.W)
+    c32, v32 = dev.traj_optimize(q, pose, opt, 1, cfg.K + 1, cfg.K)
+    c32, v32 = N(c32), N(v32)
+    ordr, _ = sp.order(T(c32), T(v32), pr.sat_eps)
+    best = int(N(ordr)[0])
+    assert res["rounds"] == int(N(info)[1]) and res["best"] == best and res["viol"] == np.float32(v32[best])
+    assert torch.equal(bq, q[best]) and torch.equal(bp, pose[best])
+    q64, p64 = o.stage2(q0, p0, cfg.K)
+    c64, v64 = o.traj_cost(q64, p64, 1, grad=False)[:2]
+    s32, s64 = v32 < pr.sat_eps, v64 < pr.sat_eps
+    decided = np.abs(v64 - pr.sat_eps) >= NEAR
+    both = (v32 >= pr.sat_eps) & (v64 >= pr.sat_eps)
+    ratio = np.abs(np.log(v32[both] / v64[both])) if both.any() else np.zeros(1)
+    report(f"tower10 solve {k}", gpu_nsat=int(s32.sum()), oracle_nsat=int(s64.sum()),
+           flags_agree=float(np.mean((s32 == s64)[decided])), within2=float(np.mean(ratio <= np.log(2.0))),
+           gpu_best_v=float(v32.min()), oracle_best_v=float(v64.min()), max_log_ratio=float(ratio.max()))
+    assert np.all((s32 == s64)[decided])
+    assert np.mean(ratio <= np.log(2.0)) >= 0.8, np.sort(ratio)[-4:]
