@@ -291,18 +291,35 @@ __device__ __forceinline__ void collide_boxes(const KProb &P, int phase, float w
                                               float (&wt)[3])
 {
     const int lane = threadIdx.x & 63;
-    // broad phase bounds: the wave's union (lo, hi) or, with HB, each half wave's (lo/hi of
-    // lanes 0-31, and a second set for lanes 32-63)
+    // broad-phase bounds: the wave's union (lo, hi) or, with HB, one box per half wave
+    // (lo, hi for lanes 0-31 and mo, mh for lanes 32-63; a half wave is one segment of 32
+    // waypoints, so two segments far apart do not make everything between them a candidate)
     float lo0, lo1, lo2, hi0, hi1, hi2, mo0 = 0.f, mo1 = 0.f, mo2 = 0.f, mh0 = 0.f, mh1 = 0.f, mh2 = 0.f;
     if constexpr (HB) {
-        const float a0 = half_reduce(lb.lo0, OpMin()), a1 = half_reduce(lb.lo1, OpMin()), a2 = half_reduce(lb.lo2, OpMin());
-        const float b0 = half_reduce(lb.hi0, OpMax()), b1 = half_reduce(lb.hi1, OpMax()), b2 = half_reduce(lb.hi2, OpMax());
         auto rl = [](float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); };
-        lo0 = rl(a0, 0); lo1 = rl(a1, 0); lo2 = rl(a2, 0); hi0 = rl(b0, 0); hi1 = rl(b1, 0); hi2 = rl(b2, 0);
-        mo0 = rl(a0, 32); mo1 = rl(a1, 32); mo2 = rl(a2, 32); mh0 = rl(b0, 32); mh1 = rl(b1, 32); mh2 = rl(b2, 32);
+        const float a0 = half_reduce(lb.lo0, OpMin()), a1 = half_reduce(lb.lo1, OpMin());
+        const float a2 = half_reduce(lb.lo2, OpMin());
+        const float b0 = half_reduce(lb.hi0, OpMax()), b1 = half_reduce(lb.hi1, OpMax());
+        const float b2 = half_reduce(lb.hi2, OpMax());
+        lo0 = rl(a0, 0);
+        lo1 = rl(a1, 0);
+        lo2 = rl(a2, 0);
+        hi0 = rl(b0, 0);
+        hi1 = rl(b1, 0);
+        hi2 = rl(b2, 0);
+        mo0 = rl(a0, 32);
+        mo1 = rl(a1, 32);
+        mo2 = rl(a2, 32);
+        mh0 = rl(b0, 32);
+        mh1 = rl(b1, 32);
+        mh2 = rl(b2, 32);
     } else {
-        lo0 = uniform(wave_min(lb.lo0)); lo1 = uniform(wave_min(lb.lo1)); lo2 = uniform(wave_min(lb.lo2));
-        hi0 = uniform(wave_max(lb.hi0)); hi1 = uniform(wave_max(lb.hi1)); hi2 = uniform(wave_max(lb.hi2));
+        lo0 = uniform(wave_min(lb.lo0));
+        lo1 = uniform(wave_min(lb.lo1));
+        lo2 = uniform(wave_min(lb.lo2));
+        hi0 = uniform(wave_max(lb.hi0));
+        hi1 = uniform(wave_max(lb.hi1));
+        hi2 = uniform(wave_max(lb.hi2));
     }
     int nar = 0;  // wave-uniform
     for (int base = 0; base < P.O; base += 64) {
@@ -1163,6 +1180,8 @@ __device__ __forceinline__ float adam_update(float x, float &m, float &v, float 
 
 // One particle per workgroup.  MODE 0: cost, 1: cost + gradient (optionally scaled per
 // particle), 2: optimise.  s_mv: dynamic LDS, [2][NJ][blockDim.x] Adam moments (MODE 2).
+// HB: a particle of 9-12 waves with a CU to itself (the 768-thread launches): the
+// obstacle broad phase bounds each half wave, and the issue-priority step is finer.
 template <int MODE, int CH, bool HB = false>
 __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a, int p, float *s_mv)
 {
