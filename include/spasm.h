@@ -392,7 +392,9 @@ int spasm_solve_ttfs(spasm_problem prob, const spasm_solve_config *cfg, int32_t 
  * own state).  Not thread-safe: one thread drives a server; the problem and output
  * buffers of a request must stay valid until its completion is polled.
  * spasm_server_submit returns SPASM_EBUSY when the request can never fit
- * (footprint > budget). */
+ * (footprint > budget).  max_slots trades latencies: with few slots a large request
+ * shares the device with fewer later ones and finishes sooner (tail latency), with many
+ * the small requests that arrive behind it start sooner (median latency). */
 typedef struct spasm_server_s *spasm_server;
 
 typedef struct {
