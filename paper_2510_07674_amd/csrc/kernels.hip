@@ -279,8 +279,8 @@ __device__ __forceinline__ LaneBox lane_box(const float (&cx)[CH], const float (
 // slowest particle; that wave takes a higher issue priority on its SIMD for the next
 // iteration (see traj_particle).
 // Narrow-phase passes per priority level (levels 0..3): 24 where a CU holds several
-// particles (their waves compete for the SIMDs), 8 for the particles of 9-12 waves that
-// have a CU to themselves (measured on 4- and 10-block towers).
+// particles (their waves compete for the SIMDs), 8 (PRIO_STEP_HB) for the particles of
+// 9-12 waves that have a CU to themselves (measured on 4- and 10-block towers).
 __shared__ int s_wave_work[16];
 constexpr int PRIO_STEP = 24, PRIO_STEP_HB = 8;
 
@@ -1180,9 +1180,10 @@ __device__ __forceinline__ float adam_update(float x, float &m, float &v, float 
 
 // One particle per workgroup.  MODE 0: cost, 1: cost + gradient (optionally scaled per
 // particle), 2: optimise.  s_mv: dynamic LDS, [2][NJ][blockDim.x] Adam moments (MODE 2).
-// HB: a particle of 9-12 waves with a CU to itself (the 768-thread launches): the
-// obstacle broad phase bounds each half wave, and the issue-priority step is finer.
-template <int MODE, int CH, bool HB = false>
+// HB: the obstacle broad phase bounds each half wave (the optimisation launches).  FINE: a
+// particle of 9-12 waves with a CU to itself (the 768-thread launches) takes the finer
+// issue-priority step.
+template <int MODE, int CH, bool HB = false, bool FINE = false>
 __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a, int p, float *s_mv)
 {
     __shared__ float s_pose[2 * MAX_B * 8];
@@ -1265,7 +1266,7 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
                 // issue priority from the previous iteration's contact work: the waves
                 // that hold their particles back run first on their SIMDs (scheduling
                 // only; the arithmetic is the same)
-                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / (HB ? PRIO_STEP_HB : PRIO_STEP);
+                const int lvl = __builtin_amdgcn_readfirstlane(s_wave_work[wave]) / (FINE ? PRIO_STEP_HB : PRIO_STEP);
                 if (lane == 0) s_wave_work[wave] = 0;
                 if (lvl >= 3)
                     __builtin_amdgcn_s_setprio(3);
@@ -1412,14 +1413,16 @@ __device__ __forceinline__ void traj_particle(const KProb &P, const TrajArgs &a,
 // BOUND: the launch bound the registers are allocated for -- 1024 threads (128 VGPRs, 16
 // waves per CU) or 768 (168 VGPRs, 12 waves per CU; fewer spills).  The optimisation
 // launch takes 768 when a CU holds as many of its particles either way (6 or 9-12 waves
-// per particle, e.g. a 10-block tower: one particle per CU); those particles' obstacle
-// broad phase bounds each half wave (one segment of 32 waypoints) on its own.
+// per particle, e.g. a 10-block tower: one particle per CU).  Every optimisation launch
+// bounds each half wave (one segment of 32 waypoints) on its own in the obstacle broad
+// phase.
 template <int MODE, int CH, int BOUND = 1024>
 __global__ __launch_bounds__(BOUND) void k_traj(KProb P, TrajArgs a)
 {
     extern __shared__ float s_mv[];
     if (a.skip && __builtin_amdgcn_readfirstlane(*a.skip)) return;
-    traj_particle<MODE, CH, BOUND == 768>(P, a, a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x, s_mv);
+    const int p = a.perm ? a.perm[a.P - 1 - (int)blockIdx.x] : (int)blockIdx.x;
+    traj_particle<MODE, CH, MODE == 2, BOUND == 768>(P, a, p, s_mv);
 }
 
 // Serving: one launch advances every active solve of one (thread count, sphere chunk)
@@ -1443,7 +1446,7 @@ __global__ __launch_bounds__(BOUND) void k_serve(const ServeSolve *solves, int n
             hi = mid - 1;
     }
     const ServeSolve &d = *(const ServeSolve *)(base + (size_t)lo * sizeof(ServeSolve));
-    traj_particle<2, CH, BOUND == 768>(d.P, d.a, wg - d.first, s_mv);
+    traj_particle<2, CH, true, BOUND == 768>(d.P, d.a, wg - d.first, s_mv);
 }
 
 // ------------------------------------------------------------------------------------
