@@ -617,8 +617,12 @@ def test_traj_init_parity(sp, orc):
 
 
 # ------------------------------------------------------------------ whole method
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_solve_tiny_free_running(sp, orc, seed):
+@pytest.mark.parametrize("k", range(8))
+def test_solve_tiny_free_running(sp, orc, k):
+    """Whole tiny solves (stage 1 to the returned particle), device against the FP64
+    oracle's own whole solve on the same scene: the same success (unless either best
+    violation lies within 1e-5 of the threshold)."""
+    seed = synth.certified_seeds("tiny")[k]
     prob, pr, cfg = synth.config("tiny", seed)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
     res, bq, bp = dev.solve(cfg)
