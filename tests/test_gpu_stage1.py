@@ -123,9 +123,9 @@ def test_stage1_rounds_vs_oracle(sp, orc, sched):
 def test_tower_solve_vs_oracle(sp, orc, k):
     """A small tower solve: the device pipeline equals its pieces bit for bit, and from the
     device's stage-1, lift and seeding state the FP64 oracle's K Adam iterations reach the
-    same success (any particle) and per-particle success flags for at least 80 % of the
-    particles (those within 1e-5 of the threshold aside), and where both stay infeasible
-    violations within a factor 2 for at least 80 % of them."""
+    same success (any particle) and per-particle success flags for at least 90 % of the
+    particles (those within 1e-5 of the threshold aside; 97-100 % measured), and where
+    both stay infeasible violations within a factor 2 for at least 80 % of them."""
     prob, pr = _problem(None, k)
     cfg = synth.SolveConfig(N1=512, M=32, W=16, K=120, seed=7)
     dev, o = sp.Problem(prob, pr), orc.Oracle(prob, pr)
@@ -150,7 +150,7 @@ def test_tower_solve_vs_oracle(sp, orc, k):
     report(f"tower solve {k}", gpu_success=int(res["success"]), gpu_nsat=int(s32.sum()), oracle_nsat=int(s64.sum()),
            agree=agree, gpu_best_v=float(v32.min()), oracle_best_v=float(v64.min()), rounds=res["rounds"])
     assert (s32.any() == s64.any()) or not decided.all()
-    assert agree >= 0.8
+    assert agree >= 0.9
     # where both runs stay infeasible their violations are of the same size (within 2x):
     # the two precisions stall in the same contact
     both = (v32 >= pr.sat_eps) & (v64 >= pr.sat_eps)
