@@ -1898,18 +1898,43 @@ __device__ __forceinline__ float arm_clutter(const KProb &P, const float (&q)[NJ
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {
         dh_step(F, P.a[J], P.d[J], P.ca[J], P.sa[J], q[J]);
+        // obstacles: those that meet no lane's bounds of the link's spheres (1e-4 m margin)
+        // contribute exactly zero and are skipped by the whole wave
+        float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
         for (int s = P.link_start[J]; s < P.link_start[J + 1]; ++s) {
             const float4 sp = ldc(P.sph, s);
             const float cx = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
             const float cy = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
             const float cz = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
-            for (int o = 0; o < P.O; ++o) {
-                const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
+            lo0 = fminf(lo0, cx - sp.w);
+            lo1 = fminf(lo1, cy - sp.w);
+            lo2 = fminf(lo2, cz - sp.w);
+            hi0 = fmaxf(hi0, cx + sp.w);
+            hi1 = fmaxf(hi1, cy + sp.w);
+            hi2 = fmaxf(hi2, cz + sp.w);
+        }
+        for (int o = 0; o < P.O; ++o) {
+            const float4 bl = ldc(P.box, 4 * o + 2), bh = ldc(P.box, 4 * o + 3);
+            if (!__any((bl.x <= hi0 + 1e-4f) & (bh.x >= lo0 - 1e-4f) & (bl.y <= hi1 + 1e-4f) & (bh.y >= lo1 - 1e-4f) &
+                       (bl.z <= hi2 + 1e-4f) & (bh.z >= lo2 - 1e-4f)))
+                continue;
+            const float4 bc = ldc(P.box, 4 * o), be = ldc(P.box, 4 * o + 1);
+            for (int s = P.link_start[J]; s < P.link_start[J + 1]; ++s) {
+                const float4 sp = ldc(P.sph, s);
+                const float cx = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
+                const float cy = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
+                const float cz = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
                 const float ux = fabsf(cx - bc.x) - be.x, uy = fabsf(cy - bc.y) - be.y, uz = fabsf(cz - bc.z) - be.z;
                 const float qx = fmaxf(ux, 0.f), qy = fmaxf(uy, 0.f), qz = fmaxf(uz, 0.f);
                 const float sdf = __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz) + fminf(fmaxf(fmaxf(ux, uy), uz), 0.f);
                 pen += fmaxf(sp.w - sdf, 0.f);
             }
+        }
+        for (int s = P.link_start[J]; s < P.link_start[J + 1]; ++s) {
+            const float4 sp = ldc(P.sph, s);
+            const float cx = F.p0 + sp.x * F.x0 + sp.y * F.y0 + sp.z * F.z0;
+            const float cy = F.p1 + sp.x * F.x1 + sp.y * F.y1 + sp.z * F.z1;
+            const float cz = F.p2 + sp.x * F.x2 + sp.y * F.y2 + sp.z * F.z2;
             for (int bb = 0; bb < (P.mode == SPASM_MODE_P2P ? 0 : P.B); ++bb) {  // p2p: no blocks
                 float tx, ty, tz, yaw;
                 if (bb < b || (bb == b && kind == 1)) {
